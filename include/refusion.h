@@ -1,0 +1,227 @@
+/*
+ * refusion.h -- C ABI of the MI355X (gfx950) implementation of the per-frame
+ * hot path of ReFusion (Palazzolo, Behley, Lottes, Giguere, Stachniss,
+ * "ReFusion: 3D Reconstruction in Dynamic Environments for RGB-D Cameras
+ * Exploiting Residuals", IROS 2019).
+ *
+ * Per frame (the processing order of the paper's Fig. 2 and Section III):
+ *   track_frame           (no mask)   initial registration, Sec. III-B
+ *   compute_dynamic_mask               residual mask + flood fill, Sec. III-C
+ *   track_frame           (with mask)  refined registration, Sec. III-C
+ *   hashmap_allocate                   block allocation incl. carve rays, Sec. III-A/III-D
+ *   integrate_frame                    running weighted average + carving, Sec. III-A/III-D
+ * and, off the per-frame path, extract_surface (the model the paper meshes).
+ *
+ * Conventions shared by every call
+ *  - All pointers named d_* and every buffer inside rf_frame are DEVICE
+ *    pointers (HIP device memory of the current device); everything else is
+ *    host memory.  The caller owns every buffer; the library keeps no pointer
+ *    past the call except the map arena (until hashmap_destroy).
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    only enqueue work; nothing synchronises except map_status,
+ *    hashmap_export's count query and rf_device_sync.
+ *  - Poses are row-major 4x4 float64 matrices, camera -> world
+ *    (y_world = R x_cam + t), stored in device memory (16 doubles).
+ *  - Images are row-major, width fastest.  Depth: uint16 (x depth_scale
+ *    metres, evaluated in FP32 as (float)raw * depth_scale) or float32 metres;
+ *    0 (or > depth_max) marks an invalid pixel.  RGB: 3 interleaved uint8 per
+ *    pixel.  Masks: uint8 per pixel, nonzero = dynamic (excluded).
+ *  - Voxel v in Z^3 has its centre at v * voxel_size; block = floor(v / 8);
+ *    a block holds 8^3 voxels with local index lx + 8 ly + 64 lz.
+ *  - Return value: RF_OK, or a negative rf_status for argument, capacity or
+ *    HIP errors detected on the host; then nothing was enqueued and
+ *    rf_last_error() describes the problem.  Conditions found on the device
+ *    (pool or hash full, degenerate tracking) are sticky bits in the map
+ *    (map_status) and in rf_track_stats; they never abort a call.
+ *  - A map must not be used from two streams at once; distinct maps are
+ *    independent.
+ */
+#ifndef REFUSION_H
+#define REFUSION_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rf_status;
+#define RF_OK 0
+#define RF_EINVAL (-1)       /* bad argument or shape */
+#define RF_ENOMEM (-2)       /* arena or caller buffer too small */
+#define RF_EDEVICE (-3)      /* a HIP runtime call failed */
+#define RF_EUNSUPPORTED (-4) /* valid request this build does not support */
+
+/* sticky device-side condition bits (map_status, rf_track_stats.flags) */
+#define RF_FLAG_POOL_FULL 0x1u        /* a block could not get a pool slot; its voxels are skipped */
+#define RF_FLAG_HASH_FULL 0x2u        /* a key found no bucket within the probe limit */
+#define RF_FLAG_TRACK_FEW_PIXELS 0x4u /* fewer than min_valid residuals: pass stopped, pose kept */
+#define RF_FLAG_TRACK_SINGULAR 0x8u   /* Cholesky pivot <= 1e-12 trace(H): pass stopped, pose kept */
+#define RF_FLAG_MASK_LIMIT 0x10u      /* flood-fill work limit reached (never expected) */
+
+#define RF_DEPTH_U16 0
+#define RF_DEPTH_F32 1
+
+#define RF_STORAGE_FP32 0    /* sdf float32 (metres), weight float32, colour RGB8 */
+#define RF_STORAGE_FP16_U8 1 /* sdf float16 of sdf/truncation, weight uint8, colour RGB8 */
+
+typedef struct {
+  float fx, fy, cx, cy;   /* pinhole intrinsics (Eq. 1) */
+  int32_t width, height;  /* pixels */
+  const void* depth;      /* device, height*width of uint16 or float32 */
+  int32_t depth_format;   /* RF_DEPTH_U16 | RF_DEPTH_F32 */
+  float depth_scale;      /* metres per uint16 unit (e.g. 0.001); ignored for float32 */
+  const uint8_t* rgb;     /* device, height*width*3 */
+} rf_frame;
+
+typedef struct {
+  float voxel_size;       /* metres (edge of one voxel) */
+  float truncation;       /* tau, metres: band half-width and the free-space value */
+  float depth_max;        /* valid depth <= depth_max; also the carving clip plane */
+  uint32_t num_buckets;   /* hash buckets, power of two */
+  uint32_t max_blocks;    /* voxel-block pool capacity */
+  uint32_t max_weight;    /* running-average weight cap, 1..255 */
+  uint32_t carve_stride;  /* pixels (u,v) with u,v = 0 mod stride cast carve rays from the camera */
+  int32_t storage;        /* RF_STORAGE_FP32 | RF_STORAGE_FP16_U8 */
+  uint32_t max_pixels;    /* largest width*height passed to compute_dynamic_mask */
+} rf_map_params;
+
+typedef struct {
+  int32_t levels;          /* coarse-to-fine levels; level l uses every 2^l-th pixel (1..8) */
+  int32_t iters_per_level; /* Gauss-Newton / LM iterations per level (fixed count) */
+  float w_c;               /* weight of the photometric term, Eq. 4 */
+  int32_t min_valid;       /* fewer residuals stop the pass (RF_FLAG_TRACK_FEW_PIXELS) */
+  double lm_lambda;        /* damping: solves (H + lambda diag H) delta = -g; 0 = Gauss-Newton */
+} rf_track_params;
+
+typedef struct {
+  float gamma;  /* residual threshold t = gamma tau^2, Sec. III-C */
+  float theta;  /* flood-fill depth ratio, Algorithm 1 */
+} rf_mask_params;
+
+typedef struct {
+  double cost;            /* sum r_d^2 + w_c r_c^2 of the last evaluated iteration */
+  double count;           /* residuals used in the last evaluated iteration */
+  int32_t iters;          /* pose updates applied */
+  uint32_t flags;         /* RF_FLAG_TRACK_* of this call */
+  double level_count[8];  /* residuals used in the first iteration of each level */
+} rf_track_stats;         /* written on the device */
+
+typedef struct rf_map rf_map; /* opaque host handle */
+
+/* ------------------------------------------------------------------------
+ * Map (Sec. III-A): sparse TSDF of 8^3-voxel blocks in an open-addressed
+ * spatial hash (linear probing, insert-only, as the paper never frees blocks).
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device memory a map with these parameters needs. */
+rf_status hashmap_bytes(const rf_map_params* p, size_t* bytes);
+
+/* Creates a map inside the caller's device arena (>= hashmap_bytes bytes,
+ * 256-byte aligned) and enqueues its initialisation (empty hash, zeroed pool).
+ * The arena stays owned by the caller and must outlive the map. */
+rf_status hashmap_create(const rf_map_params* p, void* d_arena, size_t bytes, void* stream, rf_map** out);
+
+/* Frees the host handle only. */
+rf_status hashmap_destroy(rf_map* m);
+
+/* Enqueues re-initialisation to the empty map (clears flags). */
+rf_status hashmap_reset(rf_map* m, void* stream);
+
+/* Block allocation for one frame (Sec. III-A, III-D).  For every valid pixel
+ * with d_mask == 0 (d_mask may be NULL) a block-grid DDA visits the blocks of
+ * the world segment of depths z in [max(D - tau, 0), D + tau] (pixels with
+ * u, v = 0 mod carve_stride: z in [0, D + tau], so free space up to the
+ * surface is covered); every visited block is inserted and recorded in the
+ * frame's block list used by the next integrate_frame.  Pose d_pose: device.
+ * A full pool or hash sets RF_FLAG_POOL_FULL / RF_FLAG_HASH_FULL and skips
+ * that block. */
+rf_status hashmap_allocate(rf_map* m, const rf_frame* f, const double* d_pose, const uint8_t* d_mask,
+                           void* stream);
+
+/* Integration (Sec. III-A, III-C, III-D) of the frame into every voxel of the
+ * blocks listed by the preceding hashmap_allocate: the voxel projects to the
+ * nearest pixel; eta = D - z; |eta| <= tau: sdf and colour are averaged with
+ * d = eta; eta > tau and z <= depth_max: sdf is averaged toward tau (free
+ * space); otherwise (eta < -tau, invalid or masked pixel, outside the image)
+ * the voxel is untouched.  sdf <- (W sdf + d)/(W + 1), W <- min(W + 1,
+ * max_weight); colour rounded half to even. */
+rf_status integrate_frame(rf_map* m, const rf_frame* f, const double* d_pose, const uint8_t* d_mask,
+                          void* stream);
+
+/* Direct registration of the frame to the TSDF (Sec. III-B, Eqs. 1-4):
+ * minimises sum S(T x)^2 + w_c (I_model(T x) - I(p))^2 over pixels with a
+ * defined trilinear sample (all 8 corner voxels observed) and |S| < tau,
+ * coarse to fine over `levels`, `iters_per_level` Gauss-Newton/LM steps each,
+ * left update T <- exp(delta^) T.  d_pose_inout: device, initial pose in,
+ * registered pose out.  d_mask: nullable, nonzero pixels are excluded (the
+ * second registration).  d_stats: nullable device rf_track_stats.
+ * Too few residuals or a singular system stop the call and keep the last
+ * good pose (flags in d_stats). */
+rf_status track_frame(rf_map* m, const rf_frame* f, const rf_track_params* tp, const uint8_t* d_mask,
+                      double* d_pose_inout, rf_track_stats* d_stats, void* stream);
+
+/* One evaluation of the normal equations at d_pose for pyramid level `level`
+ * (Sec. III-B): d_out29 (device) receives H (21 upper-triangle terms,
+ * row-major), g (6), cost and count as float64.  Diagnostic entry point. */
+rf_status track_normal_equations(rf_map* m, const rf_frame* f, const uint8_t* d_mask, const double* d_pose,
+                                 int32_t level, float w_c, double* d_out29, void* stream);
+
+/* Dynamic mask (Sec. III-C): residual r = S(T x)^2 at pose d_pose for every
+ * valid pixel with a defined sample; raw = r > gamma tau^2; 3x3 erosion;
+ * depth-aware flood fill (Algorithm 1: a neighbour n of a member p joins when
+ * |D(p) - D(n)| < theta D(p), 8-neighbourhood); 3x3 dilation.  Out-of-image
+ * neighbours count as 0.  d_mask_out: device uint8 width*height.
+ * d_residual_out: nullable device float32 width*height (-1 where undefined).
+ * width*height must not exceed the map's max_pixels. */
+rf_status compute_dynamic_mask(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
+                               uint8_t* d_mask_out, float* d_residual_out, void* stream);
+
+/* compute_dynamic_mask that also writes its intermediate masks (each nullable,
+ * device uint8 width*height): raw threshold, eroded seeds M_R, flood fill M_D. */
+rf_status compute_dynamic_mask_stages(rf_map* m, const rf_frame* f, const double* d_pose,
+                                      const rf_mask_params* mp, uint8_t* d_raw, uint8_t* d_eroded,
+                                      uint8_t* d_filled, uint8_t* d_mask_out, float* d_residual_out,
+                                      void* stream);
+
+/* Zero crossings of the TSDF on voxel edges (the surface the paper meshes):
+ * for voxels v and v + e_axis both observed with |sdf| < tau and opposite
+ * signs (sdf > 0 on one side only), the point v s + e_axis s sdf(v) /
+ * (sdf(v) - sdf(v + e_axis)).  d_points: device float32 cap x 7 (x, y, z,
+ * r, g, b of voxel v, axis); *d_count (device uint32) receives the total
+ * number found (may exceed cap; only cap are written).  Order arbitrary. */
+rf_status extract_surface(rf_map* m, float* d_points, uint32_t cap, uint32_t* d_count, void* stream);
+
+/* Sticky device flags (RF_FLAG_*) and allocated block count.  Synchronises
+ * the stream. */
+rf_status map_status(rf_map* m, void* stream, uint32_t* flags, uint32_t* n_blocks);
+
+/* The blocks listed by the last hashmap_allocate: d_keys (device int32,
+ * cap x 3 block coordinates); *d_count (device uint32) = list length. */
+rf_status hashmap_frame_blocks(rf_map* m, int32_t* d_keys, uint32_t cap, uint32_t* d_count, void* stream);
+
+/* Export of every allocated block (checkpoint): d_keys int32 cap x 3,
+ * d_sdf float32 cap x 512 (metres, decoded), d_weight float32 cap x 512,
+ * d_rgb uint8 cap x 512 x 3 (each device, nullable); *d_count (device) =
+ * number of blocks (order arbitrary; only cap are written). */
+rf_status hashmap_export(rf_map* m, int32_t* d_keys, float* d_sdf, float* d_weight, uint8_t* d_rgb,
+                         uint32_t cap, uint32_t* d_count, void* stream);
+
+/* Import of n blocks in hashmap_export's layout (device arrays; keys must be
+ * distinct).  Existing blocks with the same key are overwritten.  FP16
+ * storage rounds sdf/tau to nearest even. */
+rf_status hashmap_import(rf_map* m, const int32_t* d_keys, const float* d_sdf, const float* d_weight,
+                         const uint8_t* d_rgb, uint32_t n, void* stream);
+
+/* Thread-local description of the last error returned on this thread. */
+const char* rf_last_error(void);
+
+/* Library version string. */
+const char* rf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REFUSION_H */

@@ -1,0 +1,320 @@
+"""ReFusion per-frame hot path on MI355X (gfx950): Python binding.
+
+Every step runs in the HIP kernels of librefusion_hip.so through the C ABI of
+include/refusion.h; this module marshals arguments and owns device buffers
+through torch tensors (device memory and streams only).  There is no CPU
+fallback: on a machine without the built library or a GPU the calls raise.
+
+Per frame (the order of the paper's Fig. 2, Sec. III):
+    track (no mask) -> dynamic mask -> track (masked) -> allocate -> integrate
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _native as N
+from ._native import (RF_DEPTH_F32, RF_DEPTH_U16, RF_FLAG_HASH_FULL, RF_FLAG_MASK_LIMIT,  # noqa: F401
+                      RF_FLAG_POOL_FULL, RF_FLAG_TRACK_FEW_PIXELS, RF_FLAG_TRACK_SINGULAR,
+                      RF_STORAGE_FP16_U8, RF_STORAGE_FP32)
+
+__all__ = ["MapParams", "TrackParams", "MaskParams", "Frame", "Map", "Pipeline", "RefusionError",
+           "hashmap_bytes", "lib"]
+
+
+class RefusionError(RuntimeError):
+    pass
+
+
+def lib():
+    return N.load()
+
+
+def _check(rc, what):
+    if rc != N.RF_OK:
+        msg = N.load().rf_last_error().decode(errors="replace")
+        raise RefusionError("%s failed (status %d): %s" % (what, rc, msg))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise RefusionError("%s must be a CUDA (HIP) tensor" % name)
+    if not t.is_contiguous():
+        raise RefusionError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise RefusionError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise RefusionError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
+@dataclasses.dataclass
+class MapParams:
+    voxel_size: float
+    truncation: float
+    depth_max: float = 5.0
+    num_buckets: int = 1 << 20
+    max_blocks: int = 1 << 18
+    max_weight: int = 255
+    carve_stride: int = 4
+    storage: str = "fp32"            # "fp32" | "fp16"
+    max_pixels: int = 640 * 480
+
+    def c(self):
+        st = {"fp32": N.RF_STORAGE_FP32, "fp16": N.RF_STORAGE_FP16_U8}[self.storage]
+        return N.RfMapParams(self.voxel_size, self.truncation, self.depth_max, self.num_buckets, self.max_blocks,
+                             self.max_weight, self.carve_stride, st, self.max_pixels)
+
+
+@dataclasses.dataclass
+class TrackParams:
+    levels: int = 3
+    iters_per_level: int = 10
+    w_c: float = 0.025          # photometric weight (Table I)
+    min_valid: int = 64
+    lm_lambda: float = 0.0      # 0: Gauss-Newton
+
+    def c(self):
+        return N.RfTrackParams(self.levels, self.iters_per_level, self.w_c, self.min_valid, self.lm_lambda)
+
+
+@dataclasses.dataclass
+class MaskParams:
+    gamma: float = 0.5          # residual threshold weight (Table I)
+    theta: float = 0.007        # flood-fill threshold (Table I)
+
+    def c(self):
+        return N.RfMaskParams(self.gamma, self.theta)
+
+
+def hashmap_bytes(params: MapParams) -> int:
+    n = ctypes.c_size_t(0)
+    p = params.c()
+    _check(N.load().hashmap_bytes(ctypes.byref(p), ctypes.byref(n)), "hashmap_bytes")
+    return int(n.value)
+
+
+class Frame:
+    """An RGB-D frame in device memory: depth (H,W) uint16 (x depth_scale m)
+    or float32 (m); rgb (H,W,3) uint8."""
+
+    def __init__(self, depth: torch.Tensor, rgb: torch.Tensor, fx, fy, cx, cy, depth_scale=0.001):
+        _dev(depth, "depth")
+        if depth.dtype == torch.uint16 if hasattr(torch, "uint16") else False:
+            fmt = N.RF_DEPTH_U16
+        elif depth.dtype == torch.int16:
+            fmt = N.RF_DEPTH_U16   # raw 16-bit words reinterpreted as unsigned by the kernels
+        elif depth.dtype == torch.float32:
+            fmt = N.RF_DEPTH_F32
+        else:
+            raise RefusionError("depth must be uint16/int16 (millimetre words) or float32 metres")
+        if depth.dim() != 2:
+            raise RefusionError("depth must be (H, W)")
+        H, W = depth.shape
+        _dev(rgb, "rgb", torch.uint8, (H, W, 3))
+        self.depth, self.rgb = depth, rgb
+        self.W, self.H = int(W), int(H)
+        self.s = N.RfFrame(fx, fy, cx, cy, self.W, self.H, depth.data_ptr(), fmt,
+                           depth_scale if fmt == N.RF_DEPTH_U16 else 1.0, rgb.data_ptr())
+
+    @staticmethod
+    def from_numpy(depth, rgb, fx, fy, cx, cy, depth_scale=0.001, device="cuda"):
+        import numpy as np
+        if depth.dtype == np.uint16:
+            d = torch.from_numpy(np.ascontiguousarray(depth).view(np.int16)).to(device)
+        else:
+            d = torch.from_numpy(np.ascontiguousarray(depth, np.float32)).to(device)
+        c = torch.from_numpy(np.ascontiguousarray(rgb, np.uint8)).to(device)
+        return Frame(d, c, fx, fy, cx, cy, depth_scale)
+
+
+class Map:
+    """A voxel-block TSDF in a device arena owned by this object."""
+
+    def __init__(self, params: MapParams, device="cuda", stream=None):
+        self.params = params
+        self.L = N.load()
+        nbytes = hashmap_bytes(params)
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        self._arena_ptr = ctypes.c_void_p(base + off)
+        self.arena_bytes = nbytes
+        self.c_params = params.c()
+        h = ctypes.c_void_p(0)
+        _check(self.L.hashmap_create(ctypes.byref(self.c_params), self._arena_ptr, nbytes, _stream(stream),
+                                     ctypes.byref(h)), "hashmap_create")
+        self.h = h
+        self.device = self.arena.device
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.L.hashmap_destroy(h)
+            self.h = None
+
+    # ---- per-frame steps
+    def allocate(self, frame: Frame, pose: torch.Tensor, mask=None, stream=None):
+        _dev(pose, "pose", torch.float64, (4, 4))
+        if mask is not None:
+            _dev(mask, "mask", torch.uint8, (frame.H, frame.W))
+        _check(self.L.hashmap_allocate(self.h, ctypes.byref(frame.s), _ptr(pose), _ptr(mask), _stream(stream)),
+               "hashmap_allocate")
+
+    def integrate(self, frame: Frame, pose: torch.Tensor, mask=None, stream=None):
+        _dev(pose, "pose", torch.float64, (4, 4))
+        if mask is not None:
+            _dev(mask, "mask", torch.uint8, (frame.H, frame.W))
+        _check(self.L.integrate_frame(self.h, ctypes.byref(frame.s), _ptr(pose), _ptr(mask), _stream(stream)),
+               "integrate_frame")
+
+    def track(self, frame: Frame, pose: torch.Tensor, tp: TrackParams, mask=None, stats=None, stream=None):
+        """Registers the frame; pose (device float64 4x4) is updated in place.
+        stats: optional device tensor of >= 11 float64 (rf_track_stats)."""
+        _dev(pose, "pose", torch.float64, (4, 4))
+        if mask is not None:
+            _dev(mask, "mask", torch.uint8, (frame.H, frame.W))
+        if stats is not None:
+            _dev(stats, "stats")
+            if stats.numel() * stats.element_size() < ctypes.sizeof(N.RfTrackStats):
+                raise RefusionError("stats buffer too small")
+        c = tp.c()
+        _check(self.L.track_frame(self.h, ctypes.byref(frame.s), ctypes.byref(c), _ptr(mask), _ptr(pose),
+                                  _ptr(stats), _stream(stream)), "track_frame")
+
+    def normal_equations(self, frame: Frame, pose: torch.Tensor, level=0, w_c=0.025, mask=None, stream=None):
+        _dev(pose, "pose", torch.float64, (4, 4))
+        out = torch.empty(29, dtype=torch.float64, device=self.device)
+        if mask is not None:
+            _dev(mask, "mask", torch.uint8, (frame.H, frame.W))
+        _check(self.L.track_normal_equations(self.h, ctypes.byref(frame.s), _ptr(mask), _ptr(pose), level, w_c,
+                                             _ptr(out), _stream(stream)), "track_normal_equations")
+        return out
+
+    def dynamic_mask(self, frame: Frame, pose: torch.Tensor, mp: MaskParams, out=None, residual=None,
+                     stages=False, stream=None):
+        _dev(pose, "pose", torch.float64, (4, 4))
+        shape = (frame.H, frame.W)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.uint8, device=self.device)
+        _dev(out, "out", torch.uint8, shape)
+        if residual is not None:
+            _dev(residual, "residual", torch.float32, shape)
+        c = mp.c()
+        if not stages:
+            _check(self.L.compute_dynamic_mask(self.h, ctypes.byref(frame.s), _ptr(pose), ctypes.byref(c),
+                                               _ptr(out), _ptr(residual), _stream(stream)), "compute_dynamic_mask")
+            return out
+        raw = torch.empty(shape, dtype=torch.uint8, device=self.device)
+        ero = torch.empty_like(raw)
+        fil = torch.empty_like(raw)
+        _check(self.L.compute_dynamic_mask_stages(self.h, ctypes.byref(frame.s), _ptr(pose), ctypes.byref(c),
+                                                  _ptr(raw), _ptr(ero), _ptr(fil), _ptr(out), _ptr(residual),
+                                                  _stream(stream)), "compute_dynamic_mask_stages")
+        return {"raw": raw, "eroded": ero, "filled": fil, "final": out}
+
+    # ---- inspection
+    def status(self, stream=None):
+        f, n = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        _check(self.L.map_status(self.h, _stream(stream), ctypes.byref(f), ctypes.byref(n)), "map_status")
+        return int(f.value), int(n.value)
+
+    def frame_blocks(self, stream=None):
+        cap = self.params.num_buckets
+        keys = torch.empty((cap, 3), dtype=torch.int32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(self.L.hashmap_frame_blocks(self.h, _ptr(keys), cap, _ptr(cnt), _stream(stream)),
+               "hashmap_frame_blocks")
+        n = int(cnt.item())
+        return keys[:n]
+
+    def export(self, stream=None):
+        """All blocks: keys (n,3) int32, sdf (n,512) f32, weight (n,512) f32,
+        rgb (n,512,3) u8 (device tensors, pool order)."""
+        _, n = self.status(stream)
+        keys = torch.empty((max(n, 1), 3), dtype=torch.int32, device=self.device)
+        sdf = torch.empty((max(n, 1), 512), dtype=torch.float32, device=self.device)
+        w = torch.empty_like(sdf)
+        rgb = torch.empty((max(n, 1), 512, 3), dtype=torch.uint8, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(self.L.hashmap_export(self.h, _ptr(keys), _ptr(sdf), _ptr(w), _ptr(rgb), n, _ptr(cnt),
+                                     _stream(stream)), "hashmap_export")
+        return keys[:n], sdf[:n], w[:n], rgb[:n]
+
+    def import_(self, keys, sdf, weight, rgb, stream=None):
+        n = int(keys.shape[0])
+        _dev(keys, "keys", torch.int32, (n, 3))
+        _dev(sdf, "sdf", torch.float32, (n, 512))
+        _dev(weight, "weight", torch.float32, (n, 512))
+        _dev(rgb, "rgb", torch.uint8, (n, 512, 3))
+        _check(self.L.hashmap_import(self.h, _ptr(keys), _ptr(sdf), _ptr(weight), _ptr(rgb), n, _stream(stream)),
+               "hashmap_import")
+
+    def surface(self, cap=None, stream=None):
+        """Zero-crossing points (n,7) float32: x, y, z, r, g, b, axis."""
+        if cap is None:
+            _, nb = self.status(stream)
+            cap = max(1024, nb * 512 * 3 // 4)
+        pts = torch.empty((cap, 7), dtype=torch.float32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(self.L.extract_surface(self.h, _ptr(pts), cap, _ptr(cnt), _stream(stream)), "extract_surface")
+        n = int(cnt.item())
+        if n > cap:
+            return self.surface(cap=n, stream=stream)
+        return pts[:n]
+
+    def stats_counts(self):
+        """(band, free) voxel updates of the last integration (device state)."""
+        raw = self.arena[(-self.arena.data_ptr()) % 256:][:64].clone().cpu()
+        v = raw.view(torch.int64)
+        return int(v[4].item()), int(v[5].item())
+
+
+class Pipeline:
+    """The per-frame method on one map with device-resident pose and mask.
+
+    process(frame) runs: first frame -> allocate + integrate at the initial
+    pose; later frames -> track (no mask), dynamic mask, track (masked),
+    allocate, integrate (all enqueued on the current stream, no host sync).
+    """
+
+    def __init__(self, params: MapParams, tp: TrackParams, mp: MaskParams, initial_pose, dynamic=True,
+                 device="cuda"):
+        self.map = Map(params, device)
+        self.tp, self.mp = tp, mp
+        self.dynamic = dynamic
+        self.pose = torch.as_tensor(initial_pose, dtype=torch.float64).to(device).contiguous()
+        self.mask = None
+        self.stats = torch.zeros(16, dtype=torch.float64, device=device)
+        self.k = 0
+
+    def process(self, frame: Frame, stream=None):
+        m = self.map
+        if self.k == 0:
+            m.allocate(frame, self.pose, None, stream)
+            m.integrate(frame, self.pose, None, stream)
+            self.k += 1
+            return self.pose
+        m.track(frame, self.pose, self.tp, None, self.stats, stream)
+        mask = None
+        if self.dynamic:
+            if self.mask is None or tuple(self.mask.shape) != (frame.H, frame.W):
+                self.mask = torch.empty((frame.H, frame.W), dtype=torch.uint8, device=self.pose.device)
+            m.dynamic_mask(frame, self.pose, self.mp, out=self.mask, stream=stream)
+            mask = self.mask
+            m.track(frame, self.pose, self.tp, mask, self.stats, stream)
+        m.allocate(frame, self.pose, mask, stream)
+        m.integrate(frame, self.pose, mask, stream)
+        self.k += 1
+        return self.pose

@@ -1,0 +1,281 @@
+// extern "C" entry points declared in include/refusion.h: argument checks,
+// arena layout and launch orchestration.  No call allocates device memory;
+// every buffer comes from the caller (the map arena included).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "rf_device.h"
+#include "rf_internal.h"
+
+struct rf_map {
+  rf::HostMap h;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+rf_status fail(rf_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+rf_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return RF_OK;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, dirty, total;
+  uint32_t dirty_cap;
+};
+
+bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+
+rf_status validate_params(const rf_map_params* p) {
+  if (!p) return fail(RF_EINVAL, "params is NULL");
+  if (!(p->voxel_size > 0.0f) || !(p->truncation > 0.0f) || !(p->depth_max > 0.0f))
+    return fail(RF_EINVAL, "voxel_size, truncation and depth_max must be > 0");
+  if (!is_pow2(p->num_buckets) || p->num_buckets < 64) return fail(RF_EINVAL, "num_buckets must be a power of two >= 64");
+  if (p->max_blocks == 0 || p->max_blocks >= 0x7FFFFFFFu / 512u)
+    return fail(RF_EINVAL, "max_blocks must be in [1, 2^22)");
+  if (p->max_weight < 1 || p->max_weight > 255) return fail(RF_EINVAL, "max_weight must be in [1, 255]");
+  if (p->carve_stride < 1) return fail(RF_EINVAL, "carve_stride must be >= 1");
+  if (p->storage != RF_STORAGE_FP32 && p->storage != RF_STORAGE_FP16_U8) return fail(RF_EINVAL, "unknown storage");
+  if (p->max_pixels > (1u << 26)) return fail(RF_EINVAL, "max_pixels too large");
+  return RF_OK;
+}
+
+Layout layout_of(const rf_map_params* p) {
+  Layout L;
+  size_t o = 0;
+  L.st = o; o = align256(o + sizeof(rf::DevState));
+  L.buckets = o; o = align256(o + (size_t)p->num_buckets * sizeof(rf::Bucket));
+  L.block_keys = o; o = align256(o + (size_t)p->max_blocks * 8);
+  L.flist = o; o = align256(o + (size_t)p->num_buckets * 4);
+  const size_t rec = (p->storage == RF_STORAGE_FP32) ? 8 : 4;
+  L.sdfw = o; o = align256(o + (size_t)p->max_blocks * 512 * rec);
+  L.rgb = o; o = align256(o + (size_t)p->max_blocks * 512 * 4);
+  L.partials = o; o = align256(o + (size_t)rf::kTrackMaxGroups * 32 * sizeof(double));
+  L.md = o; o = align256(o + (size_t)p->max_pixels);
+  L.dirty_cap = p->max_pixels / 16 + 64;
+  L.dirty = o; o = align256(o + (size_t)L.dirty_cap * 4);
+  L.total = o;
+  return L;
+}
+
+rf_status make_frame(const rf_frame* f, rf::FrameDev& out) {
+  if (!f) return fail(RF_EINVAL, "frame is NULL");
+  if (f->width <= 0 || f->height <= 0 || (int64_t)f->width * f->height > (1 << 26))
+    return fail(RF_EINVAL, "bad frame size %dx%d", f->width, f->height);
+  if (!f->depth || !f->rgb) return fail(RF_EINVAL, "frame depth/rgb is NULL");
+  if (f->depth_format != RF_DEPTH_U16 && f->depth_format != RF_DEPTH_F32) return fail(RF_EINVAL, "bad depth_format");
+  if (!(f->fx > 0.0f) || !(f->fy > 0.0f)) return fail(RF_EINVAL, "fx, fy must be > 0");
+  if (f->depth_format == RF_DEPTH_U16 && !(f->depth_scale > 0.0f)) return fail(RF_EINVAL, "depth_scale must be > 0");
+  out.depth = f->depth;
+  out.rgb = f->rgb;
+  out.W = f->width;
+  out.H = f->height;
+  out.fx = f->fx;
+  out.fy = f->fy;
+  out.cx = f->cx;
+  out.cy = f->cy;
+  out.ifx = 1.0f / f->fx;
+  out.ify = 1.0f / f->fy;
+  out.dscale = f->depth_scale;
+  return RF_OK;
+}
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* rf_last_error(void) { return g_err; }
+
+const char* rf_version(void) { return "refusion-gfx950 1.0"; }
+
+rf_status hashmap_bytes(const rf_map_params* p, size_t* bytes) {
+  rf_status st = validate_params(p);
+  if (st) return st;
+  if (!bytes) return fail(RF_EINVAL, "bytes is NULL");
+  *bytes = layout_of(p).total;
+  return RF_OK;
+}
+
+rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void* stream, rf_map** out) {
+  rf_status st = validate_params(p);
+  if (st) return st;
+  if (!arena || !out) return fail(RF_EINVAL, "arena/out is NULL");
+  if (reinterpret_cast<uintptr_t>(arena) & 255) return fail(RF_EINVAL, "arena must be 256-byte aligned");
+  const Layout L = layout_of(p);
+  if (bytes < L.total) return fail(RF_ENOMEM, "arena has %zu bytes, needs %zu", bytes, L.total);
+  rf_map* m = new (std::nothrow) rf_map;
+  if (!m) return fail(RF_ENOMEM, "host allocation failed");
+  char* a = static_cast<char*>(arena);
+  rf::HostMap& h = m->h;
+  h.p = *p;
+  h.arena = arena;
+  h.bytes = bytes;
+  h.frame_id = 0;
+  rf::MapDev& d = h.dev;
+  d.st = reinterpret_cast<rf::DevState*>(a + L.st);
+  d.buckets = reinterpret_cast<rf::Bucket*>(a + L.buckets);
+  d.bucket_mask = p->num_buckets - 1;
+  d.max_probe = p->num_buckets < 1024 ? p->num_buckets : 1024;
+  d.block_keys = reinterpret_cast<unsigned long long*>(a + L.block_keys);
+  d.flist = reinterpret_cast<uint32_t*>(a + L.flist);
+  d.flist_cap = p->num_buckets;
+  d.max_blocks = p->max_blocks;
+  d.sdfw = a + L.sdfw;
+  d.rgb = reinterpret_cast<uchar4*>(a + L.rgb);
+  d.partials = reinterpret_cast<double*>(a + L.partials);
+  d.md = reinterpret_cast<uint8_t*>(a + L.md);
+  d.dirty = reinterpret_cast<uint32_t*>(a + L.dirty);
+  d.max_pixels = p->max_pixels;
+  d.dirty_cap = L.dirty_cap;
+  d.s = p->voxel_size;
+  d.is = 1.0f / p->voxel_size;
+  d.iB = 1.0f / (8.0f * p->voxel_size);
+  d.tau = p->truncation;
+  d.inv_tau = 1.0f / p->truncation;
+  d.dmax = p->depth_max;
+  d.max_weight = (float)p->max_weight;
+  d.carve_stride = p->carve_stride;
+  rf::launch_map_init(d, p->num_buckets, p->storage, S(stream));
+  st = check_launch("hashmap_create");
+  if (st) {
+    delete m;
+    return st;
+  }
+  *out = m;
+  return RF_OK;
+}
+
+rf_status hashmap_destroy(rf_map* m) {
+  delete m;
+  return RF_OK;
+}
+
+rf_status hashmap_reset(rf_map* m, void* stream) {
+  if (!m) return fail(RF_EINVAL, "map is NULL");
+  m->h.frame_id = 0;
+  rf::launch_map_init(m->h.dev, m->h.p.num_buckets, m->h.p.storage, S(stream));
+  return check_launch("hashmap_reset");
+}
+
+rf_status hashmap_allocate(rf_map* m, const rf_frame* f, const double* d_pose, const uint8_t* d_mask, void* stream) {
+  if (!m || !d_pose) return fail(RF_EINVAL, "map/pose is NULL");
+  rf::FrameDev fd;
+  rf_status st = make_frame(f, fd);
+  if (st) return st;
+  // frame stamps: 0 is the initial bucket value, so the epoch skips 0 on wrap
+  m->h.frame_id = (m->h.frame_id == 0xFFFFFFFFu) ? 1u : m->h.frame_id + 1u;
+  rf::launch_allocate(m->h.dev, fd, f->depth_format, d_pose, d_mask, m->h.frame_id, S(stream));
+  return check_launch("hashmap_allocate");
+}
+
+rf_status integrate_frame(rf_map* m, const rf_frame* f, const double* d_pose, const uint8_t* d_mask, void* stream) {
+  if (!m || !d_pose) return fail(RF_EINVAL, "map/pose is NULL");
+  rf::FrameDev fd;
+  rf_status st = make_frame(f, fd);
+  if (st) return st;
+  rf::launch_integrate(m->h.dev, fd, f->depth_format, m->h.p.storage, d_pose, d_mask, S(stream));
+  return check_launch("integrate_frame");
+}
+
+rf_status track_frame(rf_map* m, const rf_frame* f, const rf_track_params* tp, const uint8_t* d_mask,
+                      double* d_pose_inout, rf_track_stats* d_stats, void* stream) {
+  if (!m || !tp || !d_pose_inout) return fail(RF_EINVAL, "map/params/pose is NULL");
+  if (tp->levels < 1 || tp->levels > 8 || tp->iters_per_level < 0 || tp->iters_per_level > 1000)
+    return fail(RF_EINVAL, "levels must be in [1,8], iters_per_level in [0,1000]");
+  if (!(tp->lm_lambda >= 0.0)) return fail(RF_EINVAL, "lm_lambda must be >= 0");
+  rf::FrameDev fd;
+  rf_status st = make_frame(f, fd);
+  if (st) return st;
+  rf::launch_track(m->h.dev, fd, f->depth_format, m->h.p.storage, *tp, d_mask, d_pose_inout, d_stats, S(stream));
+  return check_launch("track_frame");
+}
+
+rf_status track_normal_equations(rf_map* m, const rf_frame* f, const uint8_t* d_mask, const double* d_pose,
+                                 int32_t level, float w_c, double* d_out29, void* stream) {
+  if (!m || !d_pose || !d_out29) return fail(RF_EINVAL, "map/pose/out is NULL");
+  if (level < 0 || level > 7) return fail(RF_EINVAL, "level must be in [0,7]");
+  rf::FrameDev fd;
+  rf_status st = make_frame(f, fd);
+  if (st) return st;
+  rf::launch_normal_equations(m->h.dev, fd, f->depth_format, m->h.p.storage, d_mask, d_pose, level, w_c, d_out29,
+                              S(stream));
+  return check_launch("track_normal_equations");
+}
+
+rf_status compute_dynamic_mask_stages(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
+                                      uint8_t* d_raw, uint8_t* d_eroded, uint8_t* d_filled, uint8_t* d_mask_out,
+                                      float* d_residual_out, void* stream) {
+  if (!m || !d_pose || !mp || !d_mask_out) return fail(RF_EINVAL, "map/pose/params/out is NULL");
+  if (!(mp->gamma >= 0.0f) || !(mp->theta >= 0.0f)) return fail(RF_EINVAL, "gamma and theta must be >= 0");
+  rf::FrameDev fd;
+  rf_status st = make_frame(f, fd);
+  if (st) return st;
+  const uint32_t npx = (uint32_t)fd.W * (uint32_t)fd.H;
+  if (npx > m->h.p.max_pixels) return fail(RF_ENOMEM, "frame has %u pixels, map max_pixels is %u", npx, m->h.p.max_pixels);
+  const uint32_t tiles = (uint32_t)((fd.W + rf::kTile - 1) / rf::kTile) * (uint32_t)((fd.H + rf::kTile - 1) / rf::kTile);
+  if (tiles > m->h.dev.dirty_cap) return fail(RF_ENOMEM, "flood-fill tile table too small");
+  rf::launch_mask(m->h.dev, fd, f->depth_format, m->h.p.storage, d_pose, *mp, d_raw, d_eroded, d_filled, d_mask_out,
+                  d_residual_out, S(stream));
+  return check_launch("compute_dynamic_mask");
+}
+
+rf_status compute_dynamic_mask(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
+                               uint8_t* d_mask_out, float* d_residual_out, void* stream) {
+  return compute_dynamic_mask_stages(m, f, d_pose, mp, nullptr, nullptr, nullptr, d_mask_out, d_residual_out, stream);
+}
+
+rf_status extract_surface(rf_map* m, float* d_points, uint32_t cap, uint32_t* d_count, void* stream) {
+  if (!m || !d_count || (cap && !d_points)) return fail(RF_EINVAL, "map/count/points is NULL");
+  rf::launch_surface(m->h.dev, m->h.p.storage, d_points, cap, d_count, S(stream));
+  return check_launch("extract_surface");
+}
+
+rf_status map_status(rf_map* m, void* stream, uint32_t* flags, uint32_t* n_blocks) {
+  if (!m) return fail(RF_EINVAL, "map is NULL");
+  rf::DevState hs;
+  hipError_t e = hipMemcpyAsync(&hs, m->h.dev.st, sizeof(hs), hipMemcpyDeviceToHost, S(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+  if (e != hipSuccess) return fail(RF_EDEVICE, "map_status: %s", hipGetErrorString(e));
+  if (flags) *flags = hs.flags;
+  if (n_blocks) *n_blocks = hs.n_blocks < m->h.p.max_blocks ? hs.n_blocks : m->h.p.max_blocks;
+  return RF_OK;
+}
+
+rf_status hashmap_frame_blocks(rf_map* m, int32_t* d_keys, uint32_t cap, uint32_t* d_count, void* stream) {
+  if (!m || !d_count || (cap && !d_keys)) return fail(RF_EINVAL, "map/count/keys is NULL");
+  rf::launch_frame_blocks(m->h.dev, d_keys, cap, d_count, S(stream));
+  return check_launch("hashmap_frame_blocks");
+}
+
+rf_status hashmap_export(rf_map* m, int32_t* d_keys, float* d_sdf, float* d_weight, uint8_t* d_rgb, uint32_t cap,
+                         uint32_t* d_count, void* stream) {
+  if (!m || !d_count) return fail(RF_EINVAL, "map/count is NULL");
+  rf::launch_export(m->h.dev, m->h.p.storage, d_keys, d_sdf, d_weight, d_rgb, cap, d_count, S(stream));
+  return check_launch("hashmap_export");
+}
+
+rf_status hashmap_import(rf_map* m, const int32_t* d_keys, const float* d_sdf, const float* d_weight,
+                         const uint8_t* d_rgb, uint32_t n, void* stream) {
+  if (!m) return fail(RF_EINVAL, "map is NULL");
+  if (n && (!d_keys || !d_sdf || !d_weight || !d_rgb)) return fail(RF_EINVAL, "import arrays are NULL");
+  rf::launch_import(m->h.dev, m->h.p.storage, d_keys, d_sdf, d_weight, d_rgb, n, S(stream));
+  return check_launch("hashmap_import");
+}
+
+}  // extern "C"

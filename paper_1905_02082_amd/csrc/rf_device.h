@@ -1,0 +1,302 @@
+// Device-side data structures and helpers shared by the gfx950 kernels.
+//
+// Map layout in the caller's HBM arena (all sections 256-byte aligned):
+//   DevState     counters and sticky flags
+//   buckets      num_buckets x 16 B  {u64 packed block key, u32 pool slot, u32 frame stamp}
+//   block_keys   max_blocks x 8 B    packed key of each pool slot
+//   flist        num_buckets x 4 B   bucket indices of the blocks the last allocation touched
+//   sdfw         max_blocks x 512 x  {f32 sdf, f32 weight} (FP32) | {f16 sdf/tau, u8 weight, pad} (FP16)
+//   rgb          max_blocks x 512 x  uchar4 (RGB + pad)
+//   partials     per-workgroup float64 normal-equation partials for tracking
+//   mask scratch max_pixels bytes + per-tile dirty flags for the flood fill
+//
+// Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
+// linear probing, insertion by 64-bit CAS on the key word (insert-only: keys
+// never change once written, so a stale read can only show EMPTY, which the
+// CAS then resolves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "refusion.h"
+
+namespace rf {
+
+constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr uint32_t kInvalidSlot = 0xFFFFFFFFu;
+constexpr int kKeyBias = 1 << 20;
+constexpr float kMaxBlockCoord = 1.0e6f;   // |block coordinate| limit (key range 2^20)
+constexpr float kMaxVoxelCoord = 8.0e6f;   // |voxel coordinate| limit (8 x 2^20 > 8e6)
+constexpr int kTrackBlock = 256;
+constexpr int kTrackMaxGroups = 512;
+constexpr int kNE = 29;                    // 21 H + 6 g + cost + count
+constexpr int kTile = 32;                  // flood-fill tile edge
+
+struct alignas(16) Bucket {
+  unsigned long long key;
+  uint32_t slot;
+  uint32_t stamp;
+};
+
+struct DevState {
+  uint32_t n_blocks;       // pool slots handed out (may exceed max_blocks when full)
+  uint32_t flags;          // sticky RF_FLAG_*
+  uint32_t f_count;        // entries in flist
+  uint32_t track_counter;  // finished workgroups of the running tracking launch
+  uint32_t track_stop;     // 1: the running registration pass stopped (degenerate)
+  uint32_t dirty_count;    // flood fill: tiles marked since the last sweep
+  uint32_t pad[2];
+  unsigned long long n_band;  // voxels updated in the band by the last integration
+  unsigned long long n_free;  // voxels carved by the last integration
+};
+
+struct MapDev {
+  Bucket* buckets;
+  uint32_t bucket_mask;
+  uint32_t max_probe;
+  unsigned long long* block_keys;
+  uint32_t* flist;
+  uint32_t flist_cap;
+  uint32_t max_blocks;
+  void* sdfw;
+  uchar4* rgb;
+  DevState* st;
+  double* partials;
+  uint8_t* md;
+  uint32_t* dirty;
+  uint32_t max_pixels;
+  uint32_t dirty_cap;
+  float s;        // voxel size
+  float is;       // 1/s
+  float iB;       // 1/(8 s)
+  float tau;
+  float inv_tau;
+  float dmax;
+  float max_weight;
+  uint32_t carve_stride;
+};
+
+struct FrameDev {
+  const void* depth;
+  const uint8_t* rgb;
+  int W, H;
+  float fx, fy, cx, cy;
+  float ifx, ify;   // 1/fx, 1/fy in FP32
+  float dscale;
+};
+
+// ---------------------------------------------------------------- keys
+__device__ __forceinline__ unsigned long long pack_key(int x, int y, int z) {
+  return ((unsigned long long)((uint32_t)(x + kKeyBias) & 0x1FFFFFu)) |
+         (((unsigned long long)((uint32_t)(y + kKeyBias) & 0x1FFFFFu)) << 21) |
+         (((unsigned long long)((uint32_t)(z + kKeyBias) & 0x1FFFFFu)) << 42);
+}
+__device__ __forceinline__ void unpack_key(unsigned long long k, int& x, int& y, int& z) {
+  x = (int)(k & 0x1FFFFFull) - kKeyBias;
+  y = (int)((k >> 21) & 0x1FFFFFull) - kKeyBias;
+  z = (int)((k >> 42) & 0x1FFFFFull) - kKeyBias;
+}
+// Teschner et al. spatial hash of the block coordinate (uint32 wrap-around).
+__device__ __forceinline__ uint32_t hash3(int x, int y, int z) {
+  return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u);
+}
+
+// Pool slot of block (x,y,z) or -1 (absent, or no slot because the pool was full).
+__device__ __forceinline__ int find_slot(const MapDev& m, int x, int y, int z) {
+  const unsigned long long key = pack_key(x, y, z);
+  uint32_t h = hash3(x, y, z) & m.bucket_mask;
+  for (uint32_t i = 0; i < m.max_probe; ++i) {
+    const Bucket b = m.buckets[h];
+    if (b.key == key) return (b.slot < m.max_blocks) ? (int)b.slot : -1;
+    if (b.key == kEmptyKey) return -1;
+    h = (h + 1) & m.bucket_mask;
+  }
+  return -1;
+}
+
+// Inserts block (x,y,z) if absent; returns its bucket index or -1 (hash full).
+__device__ __forceinline__ int insert_block(const MapDev& m, int x, int y, int z) {
+  const unsigned long long key = pack_key(x, y, z);
+  uint32_t h = hash3(x, y, z) & m.bucket_mask;
+  for (uint32_t i = 0; i < m.max_probe; ++i) {
+    unsigned long long k = m.buckets[h].key;
+    if (k == key) return (int)h;
+    if (k == kEmptyKey) {
+      unsigned long long old = atomicCAS(&m.buckets[h].key, kEmptyKey, key);
+      if (old == kEmptyKey) {
+        uint32_t slot = atomicAdd(&m.st->n_blocks, 1u);
+        if (slot < m.max_blocks) {
+          m.block_keys[slot] = key;
+        } else {
+          slot = kInvalidSlot;
+          atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
+        }
+        m.buckets[h].slot = slot;
+        return (int)h;
+      }
+      if (old == key) return (int)h;
+    }
+    h = (h + 1) & m.bucket_mask;
+  }
+  atomicOr(&m.st->flags, (uint32_t)RF_FLAG_HASH_FULL);
+  return -1;
+}
+
+// ---------------------------------------------------------------- storage
+template <int STORAGE>
+struct VoxelStore;
+
+template <>
+struct VoxelStore<RF_STORAGE_FP32> {
+  __device__ __forceinline__ static void load(const MapDev& m, uint32_t i, float& sdf, float& w) {
+    const float2 v = reinterpret_cast<const float2*>(m.sdfw)[i];
+    sdf = v.x;
+    w = v.y;
+  }
+  __device__ __forceinline__ static void store(const MapDev& m, uint32_t i, float sdf, float w) {
+    reinterpret_cast<float2*>(m.sdfw)[i] = make_float2(sdf, w);
+  }
+};
+
+template <>
+struct VoxelStore<RF_STORAGE_FP16_U8> {
+  __device__ __forceinline__ static void load(const MapDev& m, uint32_t i, float& sdf, float& w) {
+    const uint32_t v = reinterpret_cast<const uint32_t*>(m.sdfw)[i];
+    sdf = __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))) * m.tau;
+    w = (float)((v >> 16) & 0xFFu);
+  }
+  __device__ __forceinline__ static void store(const MapDev& m, uint32_t i, float sdf, float w) {
+    // The FP32 product is rounded first and then converted (two roundings, as
+    // specified); the empty asm keeps the compiler from fusing the multiply
+    // and the conversion into one mixed-precision FMA with a single rounding.
+    float q = sdf * m.inv_tau;
+    asm volatile("" : "+v"(q));
+    const unsigned short h = __half_as_ushort(__float2half_rn(q));
+    reinterpret_cast<uint32_t*>(m.sdfw)[i] = (uint32_t)h | ((uint32_t)w << 16);
+  }
+};
+
+// ---------------------------------------------------------------- frame
+template <int DF>
+__device__ __forceinline__ float load_depth(const FrameDev& f, int idx) {
+  if constexpr (DF == RF_DEPTH_U16) {
+    return (float)reinterpret_cast<const uint16_t*>(f.depth)[idx] * f.dscale;
+  } else {
+    return reinterpret_cast<const float*>(f.depth)[idx];
+  }
+}
+__device__ __forceinline__ bool depth_ok(float D, float dmax) { return D > 0.0f && D <= dmax; }
+
+// ((0.2126 R + 0.7152 G) + 0.0722 B) / 255
+__device__ __forceinline__ float luminance(float r, float g, float b) {
+  return ((0.2126f * r + 0.7152f * g) + 0.0722f * b) / 255.0f;
+}
+
+// Float copy of the FP64 pose: R row-major, t.
+__device__ __forceinline__ void load_pose_f(const double* T, float R[9], float t[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) R[3 * i + j] = (float)T[4 * i + j];
+    t[i] = (float)T[4 * i + 3];
+  }
+}
+
+// y = R x + t evaluated as ((R0 x0 + R1 x1) + R2 x2) + t (no contraction).
+__device__ __forceinline__ void xform(const float R[9], const float t[3], const float x[3], float y[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) y[i] = ((R[3 * i] * x[0] + R[3 * i + 1] * x[1]) + R[3 * i + 2] * x[2]) + t[i];
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return a + t * (b - a); }
+
+// Trilinear interpolation of corner values c[k] (k = dx + 2 dy + 4 dz) at the
+// fraction f; returns value and derivative with respect to the grid
+// coordinate (x, then y, then z lerps).
+__device__ __forceinline__ void trilinear(const float c[8], const float f[3], float& val, float dg[3],
+                                          bool grad) {
+  float cx00 = lerpf(c[0], c[1], f[0]);
+  float cx01 = lerpf(c[2], c[3], f[0]);
+  float cx10 = lerpf(c[4], c[5], f[0]);
+  float cx11 = lerpf(c[6], c[7], f[0]);
+  float cy0 = lerpf(cx00, cx01, f[1]);
+  float cy1 = lerpf(cx10, cx11, f[1]);
+  val = lerpf(cy0, cy1, f[2]);
+  if (grad) {
+    float dx00 = c[1] - c[0], dx01 = c[3] - c[2], dx10 = c[5] - c[4], dx11 = c[7] - c[6];
+    float dxy0 = lerpf(dx00, dx01, f[1]);
+    float dxy1 = lerpf(dx10, dx11, f[1]);
+    dg[0] = lerpf(dxy0, dxy1, f[2]);
+    float dy0 = cx01 - cx00, dy1 = cx11 - cx10;
+    dg[1] = lerpf(dy0, dy1, f[2]);
+    dg[2] = cy1 - cy0;
+  }
+}
+
+// Trilinear sample of the TSDF (and, with WANT_COLOUR, of the model intensity)
+// at world point y.  Defined only if all 8 corner voxels lie in allocated
+// blocks and have weight > 0.  Gradients are with respect to world
+// coordinates (d/dg * 1/s).
+template <int STORAGE, bool WANT_GRAD, bool WANT_COLOUR>
+__device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], float& S, float gS[3],
+                                           float& Iv, float gI[3]) {
+  float fr[3];
+  int i0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float g = y[a] * m.is;
+    const float fl = floorf(g);
+    if (!(fl > -kMaxVoxelCoord && fl < kMaxVoxelCoord)) return false;
+    i0[a] = (int)fl;
+    fr[a] = g - fl;
+  }
+  const int bx0 = i0[0] >> 3, by0 = i0[1] >> 3, bz0 = i0[2] >> 3;
+  const bool cx = (i0[0] & 7) == 7, cy = (i0[1] & 7) == 7, cz = (i0[2] & 7) == 7;
+  int sl[8];
+  sl[0] = find_slot(m, bx0, by0, bz0);
+  if (sl[0] < 0) return false;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+    const int e = (dx & (int)cx) | ((dy & (int)cy) << 1) | ((dz & (int)cz) << 2);
+    if (e != k) {
+      sl[k] = sl[e];
+    } else {
+      sl[k] = find_slot(m, bx0 + dx, by0 + dy, bz0 + dz);
+      if (sl[k] < 0) return false;
+    }
+  }
+  float cs[8], ci[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+    const uint32_t idx = (uint32_t)sl[k] * 512u + (uint32_t)(((i0[0] + dx) & 7) + 8 * ((i0[1] + dy) & 7) +
+                                                             64 * ((i0[2] + dz) & 7));
+    float w;
+    VoxelStore<STORAGE>::load(m, idx, cs[k], w);
+    if (!(w > 0.0f)) return false;
+    if (WANT_COLOUR) {
+      const uchar4 c = m.rgb[idx];
+      ci[k] = luminance((float)c.x, (float)c.y, (float)c.z);
+    }
+  }
+  float dg[3];
+  trilinear(cs, fr, S, dg, WANT_GRAD);
+  if (WANT_GRAD) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gS[a] = dg[a] * m.is;
+  }
+  if (WANT_COLOUR) {
+    float di[3];
+    trilinear(ci, fr, Iv, di, WANT_GRAD);
+    if (WANT_GRAD) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gI[a] = di[a] * m.is;
+    }
+  }
+  return true;
+}
+
+}  // namespace rf

@@ -1,0 +1,250 @@
+// Residual-based dynamics mask (Sec. III-C, Algorithm 1) for gfx950.
+//
+//   residual_kernel   r = S(T x)^2 per valid pixel, raw = r > gamma tau^2
+//   erode_kernel      3x3 erosion (outside the image counts as 0) -> seeds
+//   flood_tiles       every 32x32 tile (plus 1-pixel halo) in LDS grows the
+//                     seeds to its local fixpoint; a tile whose new border
+//                     pixels can reach an unset pixel of a neighbouring tile
+//                     marks that tile dirty
+//   flood_finish      one workgroup re-runs dirty tiles one at a time until
+//                     no tile is dirty: growth is monotone, so the result is
+//                     the unique least fixpoint the queue of Algorithm 1
+//                     reaches, with no grid-wide barrier
+//   dilate_kernel     3x3 dilation -> final mask
+// The flood-fill rule: a neighbour n (8-neighbourhood) of a member p joins
+// when |D(p) - D(n)| < theta D(p); invalid pixels carry D = 0 and so never
+// join nor propagate.
+#include "rf_device.h"
+#include "rf_internal.h"
+
+namespace rf {
+
+template <int DF, int STORAGE>
+__global__ __launch_bounds__(256) void residual_kernel(MapDev m, FrameDev f, const double* __restrict__ pose,
+                                                       float thr, uint8_t* __restrict__ raw,
+                                                       float* __restrict__ residual) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= f.W * f.H) return;
+  const int u = idx % f.W, v = idx / f.W;
+  const float D = load_depth<DF>(f, idx);
+  uint8_t out = 0;
+  float r = -1.0f;
+  if (depth_ok(D, m.dmax)) {
+    float R[9], t[3];
+    load_pose_f(pose, R, t);
+    const float x[3] = {(((float)u - f.cx) * f.ifx) * D, (((float)v - f.cy) * f.ify) * D, D};
+    float y[3];
+    xform(R, t, x, y);
+    float S, Iv, g3[3], h3[3];
+    if (sample_map<STORAGE, false, false>(m, y, S, g3, Iv, h3)) {
+      r = S * S;
+      out = (r > thr) ? 1 : 0;
+    }
+  }
+  raw[idx] = out;
+  if (residual) residual[idx] = r;
+}
+
+__global__ __launch_bounds__(256) void morph_kernel(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, int W,
+                                                    int H, int erode) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= W * H) return;
+  const int u = idx % W, v = idx / W;
+  int all = 1, any = 0;
+#pragma unroll
+  for (int dv = -1; dv <= 1; ++dv)
+#pragma unroll
+    for (int du = -1; du <= 1; ++du) {
+      const int nu = u + du, nv = v + dv;
+      const int val = (nu >= 0 && nv >= 0 && nu < W && nv < H) ? (in[nv * W + nu] != 0) : 0;
+      all &= val;
+      any |= val;
+    }
+  out[idx] = (uint8_t)(erode ? all : any);
+}
+
+template <int DF>
+__device__ __forceinline__ float flood_depth(const FrameDev& f, float dmax, int u, int v) {
+  if (u < 0 || v < 0 || u >= f.W || v >= f.H) return 0.0f;
+  const float D = load_depth<DF>(f, v * f.W + u);
+  return depth_ok(D, dmax) ? D : 0.0f;
+}
+
+constexpr int kHalo = kTile + 2;
+
+// Grows the seeds of tile (tx,ty) to the tile-local fixpoint.  The halo is
+// read-only input.  Returns (in LDS) whether anything changed; marks the
+// neighbouring tiles that a newly set border pixel can reach.
+template <int DF>
+__device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, int tx, int ty, int tiles_x,
+                               int tiles_y, uint8_t* s_m, uint8_t* s_m0, float* s_d, int* s_flag) {
+  const int nthr = blockDim.x;
+  const int u0 = tx * kTile - 1, v0 = ty * kTile - 1;
+  for (int i = threadIdx.x; i < kHalo * kHalo; i += nthr) {
+    const int hu = i % kHalo, hv = i / kHalo;
+    const int u = u0 + hu, v = v0 + hv;
+    const bool in = (u >= 0 && v >= 0 && u < f.W && v < f.H);
+    const uint8_t mv = in ? (m.md[v * f.W + u] != 0) : 0;
+    s_m[i] = mv;
+    s_m0[i] = mv;
+    s_d[i] = flood_depth<DF>(f, m.dmax, u, v);
+  }
+  __syncthreads();
+  for (;;) {
+    if (threadIdx.x == 0) *s_flag = 0;
+    __syncthreads();
+    int changed = 0;
+    for (int i = threadIdx.x; i < kTile * kTile; i += nthr) {
+      const int hu = 1 + (i % kTile), hv = 1 + (i / kTile);
+      const int c = hv * kHalo + hu;
+      if (s_m[c]) continue;
+      const float dq = s_d[c];
+      if (!(dq > 0.0f)) continue;
+      bool join = false;
+#pragma unroll
+      for (int dv = -1; dv <= 1; ++dv)
+#pragma unroll
+        for (int du = -1; du <= 1; ++du) {
+          if (!du && !dv) continue;
+          const int n = c + dv * kHalo + du;
+          if (s_m[n]) {
+            const float dp = s_d[n];
+            join |= fabsf(dp - dq) < theta * dp;
+          }
+        }
+      if (join) {
+        s_m[c] = 1;
+        changed = 1;
+      }
+    }
+    if (changed) *s_flag = 1;
+    __syncthreads();
+    const int again = *s_flag;
+    __syncthreads();
+    if (!again) break;
+  }
+  // write back new members; mark neighbours a new border member can reach
+  for (int i = threadIdx.x; i < kTile * kTile; i += nthr) {
+    const int lu = i % kTile, lv = i / kTile;
+    const int c = (lv + 1) * kHalo + (lu + 1);
+    if (!s_m[c] || s_m0[c]) continue;
+    const int u = u0 + 1 + lu, v = v0 + 1 + lv;
+    if (u >= f.W || v >= f.H) continue;
+    m.md[v * f.W + u] = 1;
+    if (lu != 0 && lu != kTile - 1 && lv != 0 && lv != kTile - 1) continue;
+    const float dp = s_d[c];
+    for (int dv = -1; dv <= 1; ++dv)
+      for (int du = -1; du <= 1; ++du) {
+        const int nlu = lu + du, nlv = lv + dv;
+        if (nlu >= 0 && nlu < kTile && nlv >= 0 && nlv < kTile) continue;  // inside this tile
+        const int n = (nlv + 1) * kHalo + (nlu + 1);
+        if (s_m[n]) continue;
+        const float dn = s_d[n];
+        if (!(dn > 0.0f) || !(fabsf(dp - dn) < theta * dp)) continue;
+        const int ntx = tx + (nlu < 0 ? -1 : (nlu >= kTile ? 1 : 0));
+        const int nty = ty + (nlv < 0 ? -1 : (nlv >= kTile ? 1 : 0));
+        if (ntx < 0 || nty < 0 || ntx >= tiles_x || nty >= tiles_y) continue;
+        m.dirty[nty * tiles_x + ntx] = 1;
+      }
+  }
+  __syncthreads();
+}
+
+template <int DF>
+__global__ __launch_bounds__(256) void flood_tiles_kernel(MapDev m, FrameDev f, float theta, int tiles_x,
+                                                          int tiles_y) {
+  __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
+  __shared__ float s_d[kHalo * kHalo];
+  __shared__ int s_flag;
+  const int tx = blockIdx.x, ty = blockIdx.y;
+  // skip tiles whose halo holds no member at all
+  const int u0 = tx * kTile - 1, v0 = ty * kTile - 1;
+  int any = 0;
+  for (int i = threadIdx.x; i < kHalo * kHalo; i += blockDim.x) {
+    const int u = u0 + i % kHalo, v = v0 + i / kHalo;
+    if (u >= 0 && v >= 0 && u < f.W && v < f.H) any |= m.md[v * f.W + u];
+  }
+  if (!__syncthreads_or(any)) return;
+  flood_one_tile<DF>(m, f, theta, tx, ty, tiles_x, tiles_y, s_m, s_m0, s_d, &s_flag);
+}
+
+// Single workgroup: process dirty tiles until none is left (or the work cap).
+template <int DF>
+__global__ __launch_bounds__(1024) void flood_finish_kernel(MapDev m, FrameDev f, float theta, int tiles_x,
+                                                            int tiles_y, int max_tiles_processed) {
+  __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
+  __shared__ float s_d[kHalo * kHalo];
+  __shared__ int s_flag;
+  __shared__ int s_list[1024];
+  __shared__ int s_n;
+  const int ntiles = tiles_x * tiles_y;
+  int processed = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
+      if (m.dirty[i]) {
+        m.dirty[i] = 0;
+        const int k = atomicAdd(&s_n, 1);
+        if (k < 1024) s_list[k] = i;
+        else m.dirty[i] = 1;  // no room this sweep: keep it for the next
+      }
+    }
+    __syncthreads();
+    const int n = min(s_n, 1024);
+    __syncthreads();
+    if (n == 0) break;
+    for (int k = 0; k < n; ++k) {
+      const int tile = s_list[k];
+      flood_one_tile<DF>(m, f, theta, tile % tiles_x, tile / tiles_x, tiles_x, tiles_y, s_m, s_m0, s_d, &s_flag);
+    }
+    processed += n;
+    if (processed > max_tiles_processed) {
+      if (threadIdx.x == 0) atomicOr(&m.st->flags, (uint32_t)RF_FLAG_MASK_LIMIT);
+      break;
+    }
+  }
+}
+
+__global__ void clear_u32_kernel(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void copy_u8_kernel(const uint8_t* __restrict__ a, uint8_t* __restrict__ b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+template <int DF, int STORAGE>
+static void mask_impl(const MapDev& m, const FrameDev& f, const double* pose, const rf_mask_params& mp,
+                      uint8_t* raw, uint8_t* eroded, uint8_t* filled, uint8_t* out, float* residual,
+                      hipStream_t s) {
+  const int n = f.W * f.H;
+  const int g = (n + 255) / 256;
+  const float tau = m.tau;
+  const float thr = mp.gamma * (tau * tau);
+  uint8_t* rawbuf = raw ? raw : out;
+  residual_kernel<DF, STORAGE><<<g, 256, 0, s>>>(m, f, pose, thr, rawbuf, residual);
+  morph_kernel<<<g, 256, 0, s>>>(rawbuf, m.md, f.W, f.H, 1);
+  if (eroded) copy_u8_kernel<<<g, 256, 0, s>>>(m.md, eroded, n);
+  const int tx = (f.W + kTile - 1) / kTile, ty = (f.H + kTile - 1) / kTile;
+  clear_u32_kernel<<<(tx * ty + 255) / 256, 256, 0, s>>>(m.dirty, tx * ty);
+  flood_tiles_kernel<DF><<<dim3(tx, ty), 256, 0, s>>>(m, f, mp.theta, tx, ty);
+  flood_finish_kernel<DF><<<1, 1024, 0, s>>>(m, f, mp.theta, tx, ty, 64 * tx * ty + n);
+  if (filled) copy_u8_kernel<<<g, 256, 0, s>>>(m.md, filled, n);
+  morph_kernel<<<g, 256, 0, s>>>(m.md, out, f.W, f.H, 0);
+}
+
+void launch_mask(const MapDev& m, const FrameDev& f, int df, int st, const double* pose, const rf_mask_params& mp,
+                 uint8_t* raw, uint8_t* eroded, uint8_t* filled, uint8_t* out, float* residual, hipStream_t s) {
+  if (df == RF_DEPTH_U16) {
+    if (st == RF_STORAGE_FP32) mask_impl<RF_DEPTH_U16, RF_STORAGE_FP32>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
+    else mask_impl<RF_DEPTH_U16, RF_STORAGE_FP16_U8>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
+  } else {
+    if (st == RF_STORAGE_FP32) mask_impl<RF_DEPTH_F32, RF_STORAGE_FP32>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
+    else mask_impl<RF_DEPTH_F32, RF_STORAGE_FP16_U8>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
+  }
+}
+
+}  // namespace rf

@@ -1,0 +1,319 @@
+"""GPU (HIP, gfx950) vs CPU oracle parity on seeded synthetic inputs.
+
+Bars: allocated block sets and dynamic masks bit-exact; voxel values
+bit-exact against the FP32 mirror (same FP32 decision and value order) and
+within 1e-5 m of the FP64 reference; poses within 1e-4 m / 1e-5 rad of the
+FP64 reference."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from gpu_helpers import (dev_pose, gpu_export_sorted, gpu_frame, gpu_keyset, map_params, need_gpu, orc_frame,
+                         oracle_maps, pose_error, sort_keys)
+
+pytestmark = pytest.mark.gpu
+
+
+def track_stats(stats):
+    """(iterations applied, flags) of a device rf_track_stats buffer."""
+    u = stats.cpu().numpy().view(np.uint32)
+    return int(u[4]), int(u[5])
+
+
+@pytest.fixture(scope="module")
+def rf():
+    return need_gpu()
+
+
+@pytest.fixture(scope="module")
+def room():
+    return synth.parity_room()
+
+
+@pytest.fixture(scope="module")
+def dyn_small():
+    return synth.dynamic_room(n_frames=24, width=160, height=120, n_clusters=2)
+
+
+def integrate_teacher_forced(rf, seq, frames, storage="fp32", orc_storage=0, masks=None):
+    """Integrates the given frames at ground-truth poses on the GPU and both
+    oracle maps; returns (gpu map, fp64 oracle, fp32 mirror)."""
+    m = rf.Map(map_params(rf, seq, storage))
+    o64, o32 = oracle_maps(seq, orc_storage)
+    for i, k in enumerate(frames):
+        mk = None if masks is None else masks[i]
+        g = gpu_frame(rf, seq, k)
+        P = dev_pose(seq.poses[k])
+        mt = None if mk is None else torch.from_numpy(mk).cuda()
+        m.allocate(g, P, mt)
+        m.integrate(g, P, mt)
+        fr = orc_frame(seq, k)
+        for o in (o64, o32):
+            o.allocate(fr, seq.poses[k], mk)
+            o.integrate(fr, seq.poses[k], mk)
+    torch.cuda.synchronize()
+    return m, o64, o32
+
+
+def assert_maps_match(m, o64, o32, sdf_tol=1e-5):
+    gk, gs, gw, gc = gpu_export_sorted(m)
+    k32, s32, w32, c32 = o32.export()
+    k64, s64, w64, c64 = o64.export()
+    assert np.array_equal(gk, k32) and np.array_equal(gk, k64)
+    np.testing.assert_array_equal(gs, s32.astype(np.float32))      # bit-exact vs FP32 mirror
+    np.testing.assert_array_equal(gw, w32.astype(np.float32))
+    np.testing.assert_array_equal(gc, c32)
+    assert np.max(np.abs(gs.astype(np.float64) - s64)) <= sdf_tol   # vs FP64 reference
+    np.testing.assert_array_equal(gw, w64.astype(np.float32))
+    np.testing.assert_array_equal(gc, c64)
+
+
+# ---------------------------------------------------------------- allocation
+
+def test_allocation_block_set_bit_exact(rf, room):
+    m = rf.Map(map_params(rf, room))
+    o = O.OracleMap(room.voxel_size, room.truncation, room.depth_max, 255, room.carve_stride, real_bits=32)
+    rng = np.random.default_rng(0)
+    for k in range(3):
+        mask = (rng.uniform(size=(room.height, room.width)) < 0.1).astype(np.uint8) if k == 2 else None
+        g = gpu_frame(rf, room, k)
+        m.allocate(g, dev_pose(room.poses[k]), None if mask is None else torch.from_numpy(mask).cuda())
+        F_gpu = gpu_keyset(m.frame_blocks())
+        F_orc = o.allocate(orc_frame(room, k), room.poses[k], mask)
+        assert np.array_equal(F_gpu, F_orc), k
+    flags, nb = m.status()
+    assert flags == 0 and nb == o.num_blocks
+    gk = gpu_export_sorted(m)[0]
+    assert np.array_equal(gk, o.export()[0])
+
+
+# ---------------------------------------------------------------- integration
+
+def test_integration_matches_oracle(rf, room):
+    m, o64, o32 = integrate_teacher_forced(rf, room, range(3))
+    assert_maps_match(m, o64, o32)
+    # one more frame: the update counts (band, free) agree with the mirror's
+    g = gpu_frame(rf, room, 3)
+    P = dev_pose(room.poses[3])
+    m.allocate(g, P)
+    m.integrate(g, P)
+    o64.allocate(orc_frame(room, 3), room.poses[3])
+    o64.integrate(orc_frame(room, 3), room.poses[3])
+    o32.allocate(orc_frame(room, 3), room.poses[3])
+    cnt = o32.integrate(orc_frame(room, 3), room.poses[3])
+    torch.cuda.synchronize()
+    assert m.stats_counts() == (int(cnt[0]), int(cnt[1]))
+    assert_maps_match(m, o64, o32)
+
+
+def test_integration_masked_pixels_untouched(rf, room):
+    rng = np.random.default_rng(1)
+    mask = np.zeros((room.height, room.width), np.uint8)
+    mask[30:80, 40:100] = 1
+    masks = [None, mask, (rng.uniform(size=mask.shape) < 0.3).astype(np.uint8)]
+    m, o64, o32 = integrate_teacher_forced(rf, room, range(3), masks=masks)
+    assert_maps_match(m, o64, o32)
+
+
+def test_integration_fp16_storage_matches_mirror(rf, room):
+    m, o64, o16 = integrate_teacher_forced(rf, room, range(4), storage="fp16", orc_storage=1)
+    gk, gs, gw, gc = gpu_export_sorted(m)
+    k16, s16, w16, c16 = o16.export()
+    assert np.array_equal(gk, k16)
+    np.testing.assert_array_equal(gs, s16.astype(np.float32))
+    np.testing.assert_array_equal(gw, w16.astype(np.float32))
+    np.testing.assert_array_equal(gc, c16)
+    k64, s64, w64, _ = o64.export()
+    assert np.array_equal(gk, k64)
+    obs = w64 > 0
+    err = np.abs(gs.astype(np.float64) - s64)[obs]
+    # each FP16 store of sdf/tau rounds by at most 2^-12 tau (half an ulp in
+    # [0.5, 1)); the running average carries earlier errors with factor
+    # W/(W+1), so after n updates the error is at most n 2^-12 tau
+    assert err.max() <= 4 * room.truncation * 2.0 ** -12
+
+
+# ---------------------------------------------------------------- tracking
+
+def test_normal_equations_match_oracle(rf, room):
+    m, o64, o32 = integrate_teacher_forced(rf, room, range(2))
+    rng = np.random.default_rng(2)
+    g = gpu_frame(rf, room, 2)
+    fr = orc_frame(room, 2)
+    for level in (0, 1):
+        T = O.pose_left_update(np.r_[rng.normal(size=3) * 0.005, rng.normal(size=3) * 0.003], room.poses[1])
+        ne = m.normal_equations(g, dev_pose(T), level, 0.025).cpu().numpy()
+        ne32 = o32.normal_equations(fr, T, level, 0.025)
+        ne64 = o64.normal_equations(fr, T, level, 0.025)
+        assert ne[28] == ne32[28] and ne[28] > 1000                    # identical FP32 decisions
+        scale = np.abs(ne32[:28]).max()
+        assert np.max(np.abs(ne[:28] - ne32[:28])) <= 1e-12 * scale * ne[28]
+        assert abs(ne[28] - ne64[28]) <= 0.002 * ne64[28]
+        np.testing.assert_allclose(ne[:21], ne64[:21], rtol=2e-3, atol=2e-3 * np.abs(ne64[:21]).max())
+
+
+def test_track_pose_matches_fp64_oracle(rf, room):
+    m, o64, o32 = integrate_teacher_forced(rf, room, range(1))
+    tp = rf.TrackParams(room.levels, room.iters)
+    for k in (1, 2):
+        P = dev_pose(room.poses[0])
+        stats = torch.zeros(16, dtype=torch.float64, device="cuda")
+        m.track(gpu_frame(rf, room, k), P, tp, None, stats)
+        T_ref, flags, st = o64.track(orc_frame(room, k), room.poses[0], room.levels, room.iters)
+        T_gpu = P.cpu().numpy()
+        dt, dr = pose_error(T_gpu, T_ref)
+        assert flags == 0
+        assert dt <= 1e-4 and dr <= 1e-5, (k, dt, dr)
+        iters, fl = track_stats(stats)
+        assert iters == room.levels * room.iters and fl == 0
+
+
+def test_free_running_parity_room_poses(rf, room):
+    """10 frames free-running: GPU pipeline vs FP64 oracle pipeline."""
+    tp = rf.TrackParams(room.levels, room.iters)
+    pipe = rf.Pipeline(map_params(rf, room), tp, rf.MaskParams(), room.poses[0], dynamic=True)
+    o64, o32 = oracle_maps(room)
+    T = room.poses[0]
+    for k in range(room.n):
+        pipe.process(gpu_frame(rf, room, k))
+        T, _ = O.process_frame(o64, orc_frame(room, k), T, k, room.levels, room.iters, mask_map=o32)
+        dt, dr = pose_error(pipe.pose.cpu().numpy(), T)
+        assert dt <= 1e-4 and dr <= 1e-5, (k, dt, dr)
+    assert pipe.map.status()[0] == 0
+
+
+# ---------------------------------------------------------------- dynamic mask
+
+@pytest.mark.parametrize("k", [12, 20])
+def test_dynamic_mask_stages_bit_exact(rf, dyn_small, k):
+    seq = dyn_small
+    masks = [(seq.labels[j] > 0).astype(np.uint8) for j in range(0, k, 3)]
+    m, o64, o32 = integrate_teacher_forced(rf, seq, range(0, k, 3), masks=masks)
+    g = gpu_frame(rf, seq, k)
+    res = torch.empty((seq.height, seq.width), dtype=torch.float32, device="cuda")
+    out = m.dynamic_mask(g, dev_pose(seq.poses[k]), rf.MaskParams(0.5, 0.007), residual=res, stages=True)
+    ref = o32.mask(orc_frame(seq, k), seq.poses[k], 0.5, 0.007)
+    for key in ("raw", "eroded", "filled", "final"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+    np.testing.assert_array_equal(res.cpu().numpy(), ref["residual"])
+    assert ref["raw"].sum() > 20 and ref["final"].sum() > ref["eroded"].sum()
+
+
+# ---------------------------------------------------------------- surface / checkpoint
+
+def test_extract_surface_matches_mirror(rf, room):
+    m, o64, o32 = integrate_teacher_forced(rf, room, range(3))
+    pts = m.surface().cpu().numpy().astype(np.float64)
+    ref = o32.surface()
+    assert len(pts) == len(ref) and len(ref) > 1000
+    key = lambda p: np.lexsort((p[:, 6], p[:, 2], p[:, 1], p[:, 0]))
+    np.testing.assert_array_equal(pts[key(pts)], ref[key(ref)])
+
+
+def test_export_import_roundtrip(rf, room):
+    m, _, _ = integrate_teacher_forced(rf, room, range(2))
+    keys, sdf, w, rgb = m.export()
+    m2 = rf.Map(map_params(rf, room))
+    m2.import_(keys, sdf, w, rgb)
+    a = gpu_export_sorted(m)
+    b = gpu_export_sorted(m2)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_empty_frame(rf, room):
+    m = rf.Map(map_params(rf, room))
+    z = np.zeros((room.height, room.width), np.float32)
+    g = rf.Frame.from_numpy(z, room.rgb[0], *room.intrinsics)
+    P = dev_pose(room.poses[0])
+    m.allocate(g, P)
+    m.integrate(g, P)
+    assert m.status() == (0, 0)
+    stats = torch.zeros(16, dtype=torch.float64, device="cuda")
+    m.track(g, P, rf.TrackParams(2, 3), None, stats)
+    assert np.array_equal(P.cpu().numpy(), room.poses[0])
+    iters, fl = track_stats(stats)
+    assert iters == 0 and fl & rf.RF_FLAG_TRACK_FEW_PIXELS
+    mk = m.dynamic_mask(g, P, rf.MaskParams())
+    assert int(mk.sum()) == 0
+
+
+def test_ragged_image_sizes(rf):
+    seq = synth.dynamic_room(n_frames=8, width=77, height=53, n_clusters=1)
+    masks = [None, None, None]
+    m, o64, o32 = integrate_teacher_forced(rf, seq, range(0, 6, 2), masks=masks)
+    assert_maps_match(m, o64, o32)
+    g = gpu_frame(rf, seq, 7)
+    out = m.dynamic_mask(g, dev_pose(seq.poses[7]), rf.MaskParams(), stages=True)
+    ref = o32.mask(orc_frame(seq, 7), seq.poses[7], 0.5, 0.007)
+    for key in ("raw", "eroded", "filled", "final"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+
+
+def test_pool_and_hash_full_flags(rf, room):
+    m = rf.Map(map_params(rf, room, max_blocks=50))
+    g = gpu_frame(rf, room, 0)
+    P = dev_pose(room.poses[0])
+    m.allocate(g, P)
+    m.integrate(g, P)
+    flags, nb = m.status()
+    assert flags & rf.RF_FLAG_POOL_FULL and nb == 50
+    m = rf.Map(map_params(rf, room, num_buckets=64))
+    m.allocate(g, P)
+    m.integrate(g, P)
+    flags, nb = m.status()
+    assert flags & rf.RF_FLAG_HASH_FULL and nb == 64
+
+
+def test_bad_arguments_raise(rf, room):
+    with pytest.raises(rf.RefusionError):
+        rf.Map(rf.MapParams(0.01, 0.03, num_buckets=1000))
+    m = rf.Map(map_params(rf, room))
+    g = gpu_frame(rf, room, 0)
+    with pytest.raises(rf.RefusionError):
+        m.track(g, dev_pose(room.poses[0]), rf.TrackParams(levels=9))
+    big = rf.Frame.from_numpy(np.zeros((200, 200), np.float32), np.zeros((200, 200, 3), np.uint8), 100, 100, 99, 99)
+    with pytest.raises(rf.RefusionError):
+        m.dynamic_mask(big, dev_pose(room.poses[0]), rf.MaskParams())
+
+
+# ---------------------------------------------------------------- full size (640x480)
+
+@pytest.fixture(scope="module")
+def static_seq():
+    return synth.static_room(n_frames=4)
+
+
+def test_full_size_static_room_teacher_forced(rf, static_seq):
+    seq = static_seq
+    m = rf.Map(map_params(rf, seq, max_blocks=1 << 17))
+    o32 = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=32)
+    for k in range(2):
+        g = gpu_frame(rf, seq, k)
+        P = dev_pose(seq.poses[k])
+        m.allocate(g, P)
+        F_gpu = gpu_keyset(m.frame_blocks())
+        F_orc = o32.allocate(orc_frame(seq, k), seq.poses[k])
+        assert np.array_equal(F_gpu, F_orc), k
+        m.integrate(g, P)
+        o32.integrate(orc_frame(seq, k), seq.poses[k])
+    gk, gs, gw, gc = gpu_export_sorted(m)
+    k32, s32, w32, c32 = o32.export()
+    assert np.array_equal(gk, k32)
+    np.testing.assert_array_equal(gs, s32.astype(np.float32))
+    np.testing.assert_array_equal(gw, w32.astype(np.float32))
+    np.testing.assert_array_equal(gc, c32)
+    # the registration step at full size: identical FP32 decisions, sums to FP64 rounding
+    g = gpu_frame(rf, seq, 2)
+    ne = m.normal_equations(g, dev_pose(seq.poses[1]), 0, 0.025).cpu().numpy()
+    ne32 = o32.normal_equations(orc_frame(seq, 2), seq.poses[1], 0, 0.025)
+    assert ne[28] == ne32[28] and ne[28] > 50000
+    assert np.max(np.abs(ne[:28] - ne32[:28])) <= 1e-12 * np.abs(ne32[:28]).max() * ne[28]
+    out = m.dynamic_mask(g, dev_pose(seq.poses[2]), rf.MaskParams(), stages=True)
+    ref = o32.mask(orc_frame(seq, 2), seq.poses[2], 0.5, 0.007)
+    for key in ("raw", "eroded", "filled", "final"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
