@@ -274,11 +274,20 @@ class Map:
             return self.surface(cap=n, stream=stream)
         return pts[:n]
 
+    def _state_words(self):
+        off = (-self.arena.data_ptr()) % 256
+        return self.arena[off:off + 80].clone().cpu().view(torch.int64)
+
     def stats_counts(self):
         """(band, free) voxel updates of the last integration (device state)."""
-        raw = self.arena[(-self.arena.data_ptr()) % 256:][:64].clone().cpu()
-        v = raw.view(torch.int64)
+        v = self._state_words()
         return int(v[4].item()), int(v[5].item())
+
+    def cumulative_counts(self):
+        """Since creation: (band updates, free-space updates, listed blocks
+        integrated, integrations)."""
+        v = self._state_words()
+        return tuple(int(v[i].item()) for i in range(6, 10))
 
 
 class Pipeline:

@@ -64,7 +64,7 @@ Layout layout_of(const rf_map_params* p) {
   const size_t rec = (p->storage == RF_STORAGE_FP32) ? 8 : 4;
   L.sdfw = o; o = align256(o + (size_t)p->max_blocks * 512 * rec);
   L.rgb = o; o = align256(o + (size_t)p->max_blocks * 512 * 4);
-  L.partials = o; o = align256(o + (size_t)rf::kTrackMaxGroups * 32 * sizeof(double));
+  L.partials = o; o = align256(o + (size_t)rf::kTrackScratchWords * 8);
   L.md = o; o = align256(o + (size_t)p->max_pixels);
   L.dirty_cap = p->max_pixels / 16 + 64;
   L.dirty = o; o = align256(o + (size_t)L.dirty_cap * 4);

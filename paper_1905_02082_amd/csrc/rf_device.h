@@ -7,7 +7,7 @@
 //   flist        num_buckets x 4 B   bucket indices of the blocks the last allocation touched
 //   sdfw         max_blocks x 512 x  {f32 sdf, f32 weight} (FP32) | {f16 sdf/tau, u8 weight, pad} (FP16)
 //   rgb          max_blocks x 512 x  uchar4 (RGB + pad)
-//   partials     per-workgroup float64 normal-equation partials for tracking
+//   partials     tracking: 3 buffers of 29 fixed-point accumulators (128 B apart) + 2 poses
 //   mask scratch max_pixels bytes + per-tile dirty flags for the flood fill
 //
 // Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
@@ -29,8 +29,15 @@ constexpr uint32_t kInvalidSlot = 0xFFFFFFFFu;
 constexpr int kKeyBias = 1 << 20;
 constexpr float kMaxBlockCoord = 1.0e6f;   // |block coordinate| limit (key range 2^20)
 constexpr float kMaxVoxelCoord = 8.0e6f;   // |voxel coordinate| limit (8 x 2^20 > 8e6)
-constexpr int kTrackBlock = 256;
-constexpr int kTrackMaxGroups = 512;
+#ifndef RF_TRACK_BLOCK
+#define RF_TRACK_BLOCK 256
+#endif
+#ifndef RF_ACC_COPIES
+#define RF_ACC_COPIES 16
+#endif
+constexpr int kTrackBlock = RF_TRACK_BLOCK;  // 256: 16x16 pixel tile; 512: 32x16
+constexpr int kAccCopies = RF_ACC_COPIES;    // copies of the tracking accumulators
+constexpr int kTrackScratchWords = 3 * kAccCopies * 29 * 16 + 32;  // 3 accumulator buffers + 2 poses
 constexpr int kNE = 29;                    // 21 H + 6 g + cost + count
 constexpr int kTile = 32;                  // flood-fill tile edge
 
@@ -50,6 +57,10 @@ struct DevState {
   uint32_t pad[2];
   unsigned long long n_band;  // voxels updated in the band by the last integration
   unsigned long long n_free;  // voxels carved by the last integration
+  unsigned long long cum_band;    // since create/reset: band updates
+  unsigned long long cum_free;    // since create/reset: free-space updates
+  unsigned long long cum_blocks;  // since create/reset: listed blocks integrated
+  unsigned long long cum_frames;  // since create/reset: integrations
 };
 
 struct MapDev {
@@ -114,6 +125,17 @@ __device__ __forceinline__ int find_slot(const MapDev& m, int x, int y, int z) {
     h = (h + 1) & m.bucket_mask;
   }
   return -1;
+}
+
+// Slot of the key given the bucket b read at index h (its home bucket):
+// continues the linear probe only when b holds another key.
+__device__ __forceinline__ int resolve_slot(const MapDev& m, Bucket b, unsigned long long key, uint32_t h) {
+  for (uint32_t i = 1;; ++i) {
+    if (b.key == key) return (b.slot < m.max_blocks) ? (int)b.slot : -1;
+    if (b.key == kEmptyKey || i >= m.max_probe) return -1;
+    h = (h + 1) & m.bucket_mask;
+    b = m.buckets[h];
+  }
 }
 
 // Inserts block (x,y,z) if absent; returns its bucket index or -1 (hash full).
@@ -253,20 +275,30 @@ __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], fl
     fr[a] = g - fl;
   }
   const int bx0 = i0[0] >> 3, by0 = i0[1] >> 3, bz0 = i0[2] >> 3;
-  const bool cx = (i0[0] & 7) == 7, cy = (i0[1] & 7) == 7, cz = (i0[2] & 7) == 7;
-  int sl[8];
-  sl[0] = find_slot(m, bx0, by0, bz0);
-  if (sl[0] < 0) return false;
+  const int cross = ((i0[0] & 7) == 7 ? 1 : 0) | ((i0[1] & 7) == 7 ? 2 : 0) | ((i0[2] & 7) == 7 ? 4 : 0);
+  // Corner k = dx + 2 dy + 4 dz lies in block (b0 + d) & cross; the distinct
+  // blocks are the corners k with k & ~cross == 0.  Their first probes are
+  // issued together (one round trip), and only collisions probe further.
+  unsigned long long key[8];
+  uint32_t hb[8];
+  Bucket bk[8];
 #pragma unroll
-  for (int k = 1; k < 8; ++k) {
-    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-    const int e = (dx & (int)cx) | ((dy & (int)cy) << 1) | ((dz & (int)cz) << 2);
-    if (e != k) {
-      sl[k] = sl[e];
-    } else {
-      sl[k] = find_slot(m, bx0 + dx, by0 + dy, bz0 + dz);
-      if (sl[k] < 0) return false;
+  for (int k = 0; k < 8; ++k) {
+    if ((k & ~cross) != 0) continue;
+    const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
+    key[k] = pack_key(x, y, z);
+    hb[k] = hash3(x, y, z) & m.bucket_mask;
+    bk[k] = m.buckets[hb[k]];
+  }
+  int sl[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if ((k & ~cross) != 0) {
+      sl[k] = sl[k & cross];
+      continue;
     }
+    sl[k] = resolve_slot(m, bk[k], key[k], hb[k]);
+    if (sl[k] < 0) return false;
   }
   float cs[8], ci[8];
 #pragma unroll

@@ -163,8 +163,18 @@ __global__ __launch_bounds__(256) void integrate_kernel(MapDev m, FrameDev f, co
   if (nf) atomicAdd(&s_cnt[1], nf);
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (s_cnt[0]) atomicAdd(&m.st->n_band, (unsigned long long)s_cnt[0]);
-    if (s_cnt[1]) atomicAdd(&m.st->n_free, (unsigned long long)s_cnt[1]);
+    if (s_cnt[0]) {
+      atomicAdd(&m.st->n_band, (unsigned long long)s_cnt[0]);
+      atomicAdd(&m.st->cum_band, (unsigned long long)s_cnt[0]);
+    }
+    if (s_cnt[1]) {
+      atomicAdd(&m.st->n_free, (unsigned long long)s_cnt[1]);
+      atomicAdd(&m.st->cum_free, (unsigned long long)s_cnt[1]);
+    }
+    if (blockIdx.x == 0) {
+      atomicAdd(&m.st->cum_blocks, (unsigned long long)nF);
+      atomicAdd(&m.st->cum_frames, 1ull);
+    }
   }
 }
 

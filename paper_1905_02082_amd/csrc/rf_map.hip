@@ -31,6 +31,10 @@ __global__ void init_state_kernel(DevState* st) {
     st->dirty_count = 0;
     st->n_band = 0;
     st->n_free = 0;
+    st->cum_band = 0;
+    st->cum_free = 0;
+    st->cum_blocks = 0;
+    st->cum_frames = 0;
   }
 }
 

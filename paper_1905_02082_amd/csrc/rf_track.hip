@@ -1,237 +1,398 @@
 // Direct registration to the TSDF (Sec. III-B, Eqs. 1-4) for gfx950.
 //
-// One launch per Gauss-Newton/LM iteration.  Each thread evaluates pixels of
-// the pyramid level (grid-stride), forms the depth residual S and the
-// photometric residual Iv - I with their 6-DoF Jacobians in FP32, and
-// accumulates the 29 normal-equation terms in FP64 (products of FP32 factors
-// are exact in FP64).  Workgroups reduce with wavefront butterflies and LDS
-// and write one FP64 partial each; the last workgroup to finish (agent-scope
-// counter) sums the partials in a fixed order, solves the 6x6 system by
-// Cholesky in FP64 and applies T <- exp(delta^) T to the device pose, so an
-// iteration needs no host round trip and no second launch.
+// One launch per Gauss-Newton/LM iteration, one thread per pixel of the
+// pyramid level (a workgroup covers a 16x16 pixel tile, so the voxels its
+// wavefronts gather are close together).  A thread forms the depth residual S and the photometric
+// residual Iv - I with their 6-DoF Jacobians in FP32 and parks them in LDS;
+// the workgroup then forms the 29 normal-equation terms in FP64 (products of
+// FP32 factors are exact in FP64) with a fixed-order transposed reduction
+// over its pixels, and adds them to device-wide accumulators.
+//
+// The accumulators are 96-bit fixed point (units of 2^-60) held as three
+// 32-bit chunks in 64-bit words and summed with device-scope integer atomics:
+// integer addition is associative, so the totals do not depend on the order
+// in which workgroups finish (bit-reproducible), and the chunks need no carry
+// chain, so every atomic is independent.  Workgroups spread over kAccCopies
+// copies of the accumulators (fewer atomics per address), which the reader
+// sums exactly.  Nothing in a launch waits for the
+// other workgroups: the solve of iteration j runs at the start of launch j+1,
+// redundantly in every workgroup (all read the same completed totals and run
+// the same instructions, so all obtain the same pose), overlapped with the
+// pose-independent loads of the pixel.  Accumulators rotate through three
+// buffers (read j-1, write j, clear j+1) and the pose through two, so no
+// launch reads what the same launch writes.  A one-workgroup finalize launch
+// solves the last iteration and writes the caller's pose.
 #include "rf_device.h"
 #include "rf_internal.h"
 
 namespace rf {
 
-// ---------------------------------------------------------------- FP64 pose math
-// Twist exponential: R = I + A K + B K^2, V = I + B K + C K^2, t = V rho.
-__device__ void se3_exp_dev(const double xi[6], double E[12]) {
-  const double p0 = xi[3], p1 = xi[4], p2 = xi[5];
-  const double th2 = p0 * p0 + p1 * p1 + p2 * p2;
-  double A, B, C;
-  if (th2 < 1e-4) {
-    const double t4 = th2 * th2, t6 = t4 * th2;
-    A = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t6 * (1.0 / 5040.0);
-    B = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t6 * (1.0 / 40320.0);
-    C = (1.0 / 6.0) - th2 * (1.0 / 120.0) + t4 * (1.0 / 5040.0) - t6 * (1.0 / 362880.0);
-  } else {
-    const double th = sqrt(th2);
-    const double sn = sin(th), hs = sin(0.5 * th);
-    A = sn / th;
-    B = 2.0 * hs * hs / th2;
-    C = (th - sn) / (th2 * th);
-  }
-  // K = [phi]x ; K2 = phi phi^T - th2 I
-  const double K[9] = {0, -p2, p1, p2, 0, -p0, -p1, p0, 0};
-  const double ph[3] = {p0, p1, p2};
-  double V[9];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      const double k2 = ph[i] * ph[j] - (i == j ? th2 : 0.0);
-      const double id = (i == j) ? 1.0 : 0.0;
-      E[4 * i + j] = id + A * K[3 * i + j] + B * k2;
-      V[3 * i + j] = id + B * K[3 * i + j] + C * k2;
-    }
-  for (int i = 0; i < 3; ++i) E[4 * i + 3] = V[3 * i] * xi[0] + V[3 * i + 1] * xi[1] + V[3 * i + 2] * xi[2];
-}
-
-// Solves (H + lambda diag H) x = -g with H given by its 21 upper-triangle
-// terms; false when a pivot is not above 1e-12 trace(H).
-__device__ bool cholesky_solve6(const double ne[29], double lambda, double x[6]) {
-  double L[6][6];
-  double tr = 0.0;
-  int k = 0;
-  for (int i = 0; i < 6; ++i)
-    for (int j = i; j < 6; ++j) {
-      L[j][i] = ne[k++];  // lower triangle holds H
-      if (i == j) tr += L[i][i];
-    }
-  for (int i = 0; i < 6; ++i) L[i][i] *= (1.0 + lambda);
-  for (int c = 0; c < 6; ++c) {
-    double piv = L[c][c];
-    for (int q = 0; q < c; ++q) piv -= L[c][q] * L[c][q];
-    if (!(piv > 1e-12 * tr)) return false;
-    const double d = sqrt(piv);
-    L[c][c] = d;
-    const double inv = 1.0 / d;
-    for (int r = c + 1; r < 6; ++r) {
-      double a = L[r][c];
-      for (int q = 0; q < c; ++q) a -= L[r][q] * L[c][q];
-      L[r][c] = a * inv;
-    }
-  }
-  double y[6];
-  for (int r = 0; r < 6; ++r) {
-    double a = -ne[21 + r];
-    for (int q = 0; q < r; ++q) a -= L[r][q] * y[q];
-    y[r] = a / L[r][r];
-  }
-  for (int r = 5; r >= 0; --r) {
-    double a = y[r];
-    for (int q = r + 1; q < 6; ++q) a -= L[q][r] * x[q];
-    x[r] = a / L[r][r];
-  }
-  return true;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+constexpr double kFixScale = 0x1p60;
+constexpr int kTermWords = 16;                     // one 128-byte line per term
+constexpr int kCopyWords = kNE * kTermWords;       // one copy of the 29 accumulators
+constexpr int kBufWords = kAccCopies * kCopyWords;  // one accumulator buffer
+constexpr int kTerms = 15;                         // J_d(6) J_c(6) r_d r_c used
+constexpr int kGroups = kTrackBlock / 32;          // LDS reduction groups per term
+constexpr int kTileW = kTrackBlock / 16;           // pixel tile: kTileW x 16
 
 struct TrackArgs {
-  int level;
+  int level;         // pyramid level evaluated by this launch (-1: none)
   float w_c;
   int min_valid;
   double lm_lambda;
-  int first_of_level;
-  int mode;  // 0: solve and update the pose; 1: write the normal equations to out29
+  int solve;         // 1: first solve the system accumulated by the previous launch
+  int prev_level;    // level of that previous evaluation
+  int prev_first;    // it was the first iteration of its level
+  int acc_read, acc_write, acc_clear;  // accumulator buffer indices (-1: none)
+  int pose_read, pose_write;           // 0/1: pose scratch, 2: caller's pose (-1: none)
+  int mode;          // 0: track; 1: write the normal equations of acc_read to out29
 };
+
+__device__ __forceinline__ unsigned long long* acc_buf(const MapDev& m, int b) {
+  return reinterpret_cast<unsigned long long*>(m.partials) + (size_t)b * kBufWords;
+}
+__device__ __forceinline__ double* pose_buf(const MapDev& m, double* user, int b) {
+  return b == 2 ? user : reinterpret_cast<double*>(m.partials) + (size_t)3 * kBufWords + 16 * b;
+}
+
+// Adds v to a term: v 2^60 truncated toward zero as a 96-bit two's
+// complement integer c0 + c1 2^32 + c2 2^64 (c0, c1 unsigned 32-bit, c2 signed).
+__device__ __forceinline__ void fixed_add(unsigned long long* acc, double v) {
+  double a = fabs(v) * kFixScale;
+  if (!(a < 0x1p94)) a = 0.0;  // non-finite or out of range: contributes nothing
+  const double hi_d = floor(a * 0x1p-64);
+  unsigned long long hi = (unsigned long long)hi_d;
+  unsigned long long lo = (unsigned long long)(a - hi_d * 0x1p64);
+  if (v < 0.0) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  const unsigned long long c0 = lo & 0xFFFFFFFFull, c1 = lo >> 32, c2 = hi;
+  if (c0) atomicAdd(&acc[0], c0);
+  if (c1) atomicAdd(&acc[1], c1);
+  if (c2) atomicAdd(&acc[2], c2);
+}
+
+// Total of a term over the accumulator copies as FP64 (exact integer sums and
+// 128-bit combination, one final rounding).
+__device__ __forceinline__ double fixed_total(const unsigned long long* acc) {
+  unsigned long long s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+  for (int c = 0; c < kAccCopies; ++c) {
+    s0 += acc[c * kCopyWords];
+    s1 += acc[c * kCopyWords + 1];
+    s2 += acc[c * kCopyWords + 2];
+  }
+  unsigned long long lo = s0 + (s1 << 32);
+  unsigned long long hi = s2 + (s1 >> 32) + (lo < s0 ? 1ull : 0ull);
+  const bool neg = (long long)hi < 0;
+  if (neg) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  const double mag = ((double)hi * 0x1p64 + (double)lo) * (1.0 / kFixScale);
+  return neg ? -mag : mag;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int tri_index(int i, int j) {  // H(i,j), i <= j, packed upper triangle
+  return 6 * i - (i * (i - 1)) / 2 + (j - i);
+}
+
+// Wavefront 0 of a workgroup: totals -> delta by row-parallel elimination
+// (lane r holds row r of [H + lambda diag H | -g]; no pivoting, H is
+// symmetric positive semi-definite) -> exp(delta^) T.  Writes the new pose
+// (row-major 12 values) to s_T and the outcome to *s_state:
+// 0 ok, RF_FLAG_TRACK_FEW_PIXELS or RF_FLAG_TRACK_SINGULAR (pose kept).
+// A pivot of the elimination equals the squared Cholesky pivot, so the
+// singularity test is the Cholesky one: pivot <= 1e-12 trace(H).
+__device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const double* Tin, double* s_T,
+                                  int* s_state) {
+  const int lane = threadIdx.x;
+  int state = 0;
+  if (s_ne[28] < (double)a.min_valid) state = RF_FLAG_TRACK_FEW_PIXELS;
+  double tr = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) tr += s_ne[tri_index(i, i)];
+  const int r = lane < 6 ? lane : 5;
+  double row[7];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) row[c] = s_ne[r <= c ? tri_index(r, c) : tri_index(c, r)];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    if (c == r) row[c] *= (1.0 + a.lm_lambda);
+  row[6] = -s_ne[21 + r];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double piv = readlane_f64(row[k], k);
+    if (!(piv > 1e-12 * tr) && state == 0) state = RF_FLAG_TRACK_SINGULAR;
+    double pk[7];
+#pragma unroll
+    for (int c = k + 1; c < 7; ++c) pk[c] = readlane_f64(row[c], k);
+    if (lane > k && lane < 6 && state == 0) {
+      const double fct = row[k] / piv;
+#pragma unroll
+      for (int c = k + 1; c < 7; ++c) row[c] = fma(-fct, pk[c], row[c]);
+    }
+  }
+  double x[6] = {0, 0, 0, 0, 0, 0};
+  if (state == 0) {
+#pragma unroll
+    for (int k = 5; k >= 0; --k) {
+      double s = readlane_f64(row[6], k);
+#pragma unroll
+      for (int j = k + 1; j < 6; ++j) s = fma(-readlane_f64(row[j], k), x[j], s);
+      x[k] = s / readlane_f64(row[k], k);
+    }
+  }
+  if (lane < 16) {
+    double out;
+    if (lane >= 12) {
+      out = (lane == 15) ? 1.0 : 0.0;
+    } else if (state != 0) {
+      out = Tin[lane];
+    } else {
+      // exp of the twist (rho, phi) = x: R = I + A K + B K^2, t = (I + B K + C K^2) rho
+      const double p0 = x[3], p1 = x[4], p2 = x[5];
+      const double th2 = p0 * p0 + p1 * p1 + p2 * p2;
+      double A, B, C;
+      if (th2 < 1e-4) {
+        const double t4 = th2 * th2, t6 = t4 * th2;
+        A = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t6 * (1.0 / 5040.0);
+        B = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t6 * (1.0 / 40320.0);
+        C = (1.0 / 6.0) - th2 * (1.0 / 120.0) + t4 * (1.0 / 5040.0) - t6 * (1.0 / 362880.0);
+      } else {
+        const double th = sqrt(th2), sn = sin(th), hs = sin(0.5 * th);
+        A = sn / th;
+        B = 2.0 * hs * hs / th2;
+        C = (th - sn) / (th2 * th);
+      }
+      const double ph[3] = {p0, p1, p2};
+      const int er = lane >> 2, ec = lane & 3;
+      // row er of E = exp: E[er][q] for q = 0..2 (rotation) and E[er][3] (translation)
+      double E[4];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        double K = 0.0;  // [phi]x (er, q)
+        if (er == 0 && q == 1) K = -p2;
+        if (er == 0 && q == 2) K = p1;
+        if (er == 1 && q == 0) K = p2;
+        if (er == 1 && q == 2) K = -p0;
+        if (er == 2 && q == 0) K = -p1;
+        if (er == 2 && q == 1) K = p0;
+        const double K2 = ph[er] * ph[q] - (er == q ? th2 : 0.0);
+        E[q] = (er == q ? 1.0 : 0.0) + A * K + B * K2;
+      }
+      {
+        const double rho[3] = {x[0], x[1], x[2]};
+        const double cr[3] = {p1 * rho[2] - p2 * rho[1], p2 * rho[0] - p0 * rho[2], p0 * rho[1] - p1 * rho[0]};
+        const double ccr[3] = {p1 * cr[2] - p2 * cr[1], p2 * cr[0] - p0 * cr[2], p0 * cr[1] - p1 * cr[0]};
+        E[3] = rho[er] + B * cr[er] + C * ccr[er];
+      }
+      out = E[0] * Tin[ec] + E[1] * Tin[4 + ec] + E[2] * Tin[8 + ec];
+      if (ec == 3) out += E[3];
+    }
+    s_T[lane] = out;
+  }
+  if (lane == 0) *s_state = state;
+}
+
+// The solve step shared by the tracking and finalize launches, run by
+// wavefront 0: reads the accumulated totals, solves, and (workgroup 0 only)
+// publishes the pose, the statistics and, on a degenerate system, the stop
+// flag.  Returns through LDS: s_T (new pose), *s_state.
+__device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& a, rf_track_stats* stats,
+                           double* s_ne, double* s_T, int* s_state, bool publish) {
+  const int lane = threadIdx.x;
+  if (lane < kNE) s_ne[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const double* Tin = pose_buf(m, user_pose, a.pose_read);
+  solve_update_wave(s_ne, a, Tin, s_T, s_state);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (!publish) return;
+  const int state = *s_state;
+  if (lane < 16) {
+    double* Tout = pose_buf(m, user_pose, a.pose_write);
+    Tout[lane] = s_T[lane];
+    if (state != 0 && a.pose_write != 2) pose_buf(m, user_pose, 1 - a.pose_write)[lane] = s_T[lane];
+  }
+  if (lane == 0) {
+    if (stats) {
+      stats->cost = s_ne[27];
+      stats->count = s_ne[28];
+      if (a.prev_first && a.prev_level >= 0 && a.prev_level < 8) stats->level_count[a.prev_level] = s_ne[28];
+      if (state == 0) stats->iters += 1;
+      else stats->flags |= (uint32_t)state;
+    }
+    if (state != 0) {
+      m.st->track_stop = 1;
+      atomicOr(&m.st->flags, (uint32_t)state);
+    }
+  }
+}
 
 template <int DF, int STORAGE>
 __global__ __launch_bounds__(kTrackBlock) void track_kernel(MapDev m, FrameDev f, const uint8_t* __restrict__ mask,
-                                                            double* __restrict__ pose, TrackArgs a,
-                                                            rf_track_stats* __restrict__ stats,
-                                                            double* __restrict__ out29) {
-  __shared__ int s_stop;
-  __shared__ int s_last;
-  __shared__ double s_wave[kTrackBlock / 64][32];
-  __shared__ double s_grp[8][32];
-  if (threadIdx.x == 0) s_stop = (a.mode == 0) ? (int)m.st->track_stop : 0;
-  __syncthreads();
-  if (s_stop) return;
+                                                            double* user_pose, TrackArgs a,
+                                                            rf_track_stats* __restrict__ stats) {
+  __shared__ float s_t[kTerms][kTrackBlock + 1];
+  __shared__ double s_g[kNE][kGroups + 1];
+  __shared__ double s_ne[kNE];
+  __shared__ double s_T[16];
+  __shared__ int s_state;
+  if (m.st->track_stop) return;  // uniform: set only by earlier launches
 
-  float R[9], t[3];
-  load_pose_f(pose, R, t);
+  // pose-independent loads first, so their latency overlaps the solve
+  // workgroup = kTileW x 16 tile of the level's pixel grid, wavefront = 8x8 sub-tile
   const int lv = a.level;
   const int wl = (f.W + (1 << lv) - 1) >> lv;
   const int hl = (f.H + (1 << lv) - 1) >> lv;
-  const int npx = wl * hl;
-  const double wc = (double)a.w_c;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tiles_x = (wl + kTileW - 1) / kTileW;
+  const int ul = (blockIdx.x % tiles_x) * kTileW + (wave % (kTileW / 8)) * 8 + (lane & 7);
+  const int vl = (blockIdx.x / tiles_x) * 16 + (wave / (kTileW / 8)) * 8 + (lane >> 3);
+  bool live = false;
+  int u = 0, v = 0, pix = 0;
+  float D = 0.0f, Ipix = 0.0f;
+  if (ul < wl && vl < hl) {
+    u = ul << lv;
+    v = vl << lv;
+    pix = v * f.W + u;
+    D = load_depth<DF>(f, pix);
+    live = depth_ok(D, m.dmax) && !(mask && mask[pix]);
+    if (live) {
+      const uint8_t* px = f.rgb + 3 * pix;
+      Ipix = luminance((float)px[0], (float)px[1], (float)px[2]);
+    }
+  }
+  if (blockIdx.x == 0 && a.acc_clear >= 0) {
+    unsigned long long* c = acc_buf(m, a.acc_clear);
+    for (int q = threadIdx.x; q < kBufWords; q += kTrackBlock) c[q] = 0ull;
+  }
+  if (threadIdx.x < 64) {
+    if (a.solve) {
+      solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, blockIdx.x == 0);
+    } else {
+      const double* Tin = pose_buf(m, user_pose, a.pose_read);
+      if (threadIdx.x < 16) {
+        s_T[threadIdx.x] = Tin[threadIdx.x];
+        if (blockIdx.x == 0) pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
+      }
+      if (threadIdx.x == 0) s_state = 0;
+    }
+  }
+  __syncthreads();
+  if (s_state != 0) return;  // degenerate: pose kept, the pass stops
 
-  double acc[kNE];
+  float term[kTerms];
 #pragma unroll
-  for (int k = 0; k < kNE; ++k) acc[k] = 0.0;
-
-  for (int i = blockIdx.x * kTrackBlock + threadIdx.x; i < npx; i += gridDim.x * kTrackBlock) {
-    const int u = (i % wl) << lv, v = (i / wl) << lv;
-    const int pix = v * f.W + u;
-    const float D = load_depth<DF>(f, pix);
-    if (!depth_ok(D, m.dmax)) continue;
-    if (mask && mask[pix]) continue;
+  for (int k = 0; k < kTerms; ++k) term[k] = 0.0f;
+  if (live) {
+    float R[9], t[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) R[3 * r + c] = (float)s_T[4 * r + c];
+      t[r] = (float)s_T[4 * r + 3];
+    }
     const float x[3] = {(((float)u - f.cx) * f.ifx) * D, (((float)v - f.cy) * f.ify) * D, D};
     float y[3];
     xform(R, t, x, y);
     float S, gS[3], Iv, gI[3];
-    if (!sample_map<STORAGE, true, true>(m, y, S, gS, Iv, gI)) continue;
-    if (!(fabsf(S) < m.tau)) continue;
-    const uint8_t* px = f.rgb + 3 * pix;
-    const float rc = Iv - luminance((float)px[0], (float)px[1], (float)px[2]);
-    const double Jd[6] = {gS[0], gS[1], gS[2], y[1] * gS[2] - y[2] * gS[1], y[2] * gS[0] - y[0] * gS[2],
-                          y[0] * gS[1] - y[1] * gS[0]};
-    const double Jc[6] = {gI[0], gI[1], gI[2], y[1] * gI[2] - y[2] * gI[1], y[2] * gI[0] - y[0] * gI[2],
-                          y[0] * gI[1] - y[1] * gI[0]};
-    const double rd = S, rcd = rc;
-    int k = 0;
+    if (sample_map<STORAGE, true, true>(m, y, S, gS, Iv, gI) && fabsf(S) < m.tau) {
+      term[0] = gS[0];
+      term[1] = gS[1];
+      term[2] = gS[2];
+      term[3] = y[1] * gS[2] - y[2] * gS[1];
+      term[4] = y[2] * gS[0] - y[0] * gS[2];
+      term[5] = y[0] * gS[1] - y[1] * gS[0];
+      term[6] = gI[0];
+      term[7] = gI[1];
+      term[8] = gI[2];
+      term[9] = y[1] * gI[2] - y[2] * gI[1];
+      term[10] = y[2] * gI[0] - y[0] * gI[2];
+      term[11] = y[0] * gI[1] - y[1] * gI[0];
+      term[12] = S;
+      term[13] = Iv - Ipix;
+      term[14] = 1.0f;
+    }
+  }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      const double wJc = wc * Jc[r];
-#pragma unroll
-      for (int c = r; c < 6; ++c) {
-        acc[k] = fma(Jd[r], Jd[c], acc[k]);
-        acc[k] = fma(wJc, Jc[c], acc[k]);
-        ++k;
+  for (int k = 0; k < kTerms; ++k) s_t[k][threadIdx.x] = term[k];
+  __syncthreads();
+
+  // thread (k, g) sums term k over pixels g, g + kGroups, ... in a fixed order
+  const double wc = (double)a.w_c;
+  if (threadIdx.x < kNE * kGroups) {
+    const int k = threadIdx.x % kNE, g = threadIdx.x / kNE;
+    int r = 0, c = 12;
+    if (k < 21) {
+      int kk = k;
+      while (kk >= 6 - r) {
+        kk -= 6 - r;
+        ++r;
       }
-      acc[21 + r] = fma(Jd[r], rd, acc[21 + r]);
-      acc[21 + r] = fma(wJc, rcd, acc[21 + r]);
+      c = r + kk;
+    } else if (k < 27) {
+      r = k - 21;
     }
-    acc[27] = fma(rd, rd, acc[27]);
-    acc[27] = fma(wc * rcd, rcd, acc[27]);
-    acc[28] += 1.0;
-  }
-
-  // workgroup reduction: wavefront butterflies, then the 4 wave sums in order
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kNE; ++k) {
-    const double v = wave_sum(acc[k]);
-    if (lane == 0) s_wave[wave][k] = v;
+    double acc = 0.0;
+    for (int p = g; p < kTrackBlock; p += kGroups) {
+      if (k < 21) {
+        acc = fma((double)s_t[r][p], (double)s_t[c][p], acc);
+        acc = fma(wc * (double)s_t[6 + r][p], (double)s_t[6 + c][p], acc);
+      } else if (k < 27) {
+        acc = fma((double)s_t[r][p], (double)s_t[12][p], acc);
+        acc = fma(wc * (double)s_t[6 + r][p], (double)s_t[13][p], acc);
+      } else if (k == 27) {
+        acc = fma((double)s_t[12][p], (double)s_t[12][p], acc);
+        acc = fma(wc * (double)s_t[13][p], (double)s_t[13][p], acc);
+      } else {
+        acc += (double)s_t[14][p];
+      }
+    }
+    s_g[k][g] = acc;
   }
   __syncthreads();
-  double* part = m.partials + (size_t)blockIdx.x * 32;
   if (threadIdx.x < kNE) {
-    double v = 0.0;
+    double tot = 0.0;
 #pragma unroll
-    for (int w = 0; w < kTrackBlock / 64; ++w) v += s_wave[w][threadIdx.x];
-    part[threadIdx.x] = v;
+    for (int g = 0; g < kGroups; ++g) tot += s_g[threadIdx.x][g];
+    fixed_add(acc_buf(m, a.acc_write) + (blockIdx.x % kAccCopies) * kCopyWords + threadIdx.x * kTermWords, tot);
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(&m.st->track_counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
 
-  // last workgroup: fixed-order sum of the partials, 8 strided groups per term
-  if (threadIdx.x < 8 * kNE) {
-    const int c = threadIdx.x % kNE, g = threadIdx.x / kNE;
-    double v = 0.0;
-    for (int b = g; b < (int)gridDim.x; b += 8) v += m.partials[(size_t)b * 32 + c];
-    s_grp[g][c] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  m.st->track_counter = 0;
-  double ne[kNE];
-  for (int c = 0; c < kNE; ++c) {
-    double v = 0.0;
-    for (int g = 0; g < 8; ++g) v += s_grp[g][c];
-    ne[c] = v;
-  }
+// Solve of the last evaluation of a pass (or, in mode 1, the raw totals).
+__global__ __launch_bounds__(64) void track_finalize_kernel(MapDev m, double* user_pose, TrackArgs a,
+                                                            rf_track_stats* stats, double* out29) {
+  __shared__ double s_ne[kNE];
+  __shared__ double s_T[16];
+  __shared__ int s_state;
   if (a.mode == 1) {
-    for (int c = 0; c < kNE; ++c) out29[c] = ne[c];
+    if (threadIdx.x < kNE) out29[threadIdx.x] = fixed_total(acc_buf(m, a.acc_read) + threadIdx.x * kTermWords);
     return;
   }
-  if (stats) {
-    stats->cost = ne[27];
-    stats->count = ne[28];
-    if (a.first_of_level && lv < 8) stats->level_count[lv] = ne[28];
-  }
-  uint32_t fl = 0;
-  double delta[6];
-  if (ne[28] < (double)a.min_valid) fl = RF_FLAG_TRACK_FEW_PIXELS;
-  else if (!cholesky_solve6(ne, a.lm_lambda, delta)) fl = RF_FLAG_TRACK_SINGULAR;
-  if (fl) {
-    m.st->track_stop = 1;
-    atomicOr(&m.st->flags, fl);
-    if (stats) stats->flags |= fl;
+  if (m.st->track_stop) {
+    // stopped earlier: both scratch poses hold the last good pose
+    if (threadIdx.x < 16) user_pose[threadIdx.x] = pose_buf(m, user_pose, a.pose_read)[threadIdx.x];
     return;
   }
-  double E[12], T[16];
-  se3_exp_dev(delta, E);
-  for (int i = 0; i < 16; ++i) T[i] = pose[i];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 4; ++j) {
-      double v = E[4 * i] * T[j] + E[4 * i + 1] * T[4 + j] + E[4 * i + 2] * T[8 + j];
-      if (j == 3) v += E[4 * i + 3];
-      pose[4 * i + j] = v;
-    }
-  if (stats) stats->iters += 1;
+  solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, true);
 }
 
 __global__ void track_reset_kernel(MapDev m, rf_track_stats* stats) {
+  unsigned long long* acc = acc_buf(m, 0);
+  for (int q = threadIdx.x; q < 3 * kBufWords; q += blockDim.x) acc[q] = 0ull;
   if (threadIdx.x == 0) {
     m.st->track_stop = 0;
     m.st->track_counter = 0;
@@ -248,42 +409,78 @@ __global__ void track_reset_kernel(MapDev m, rf_track_stats* stats) {
 static int track_grid(const FrameDev& f, int level) {
   const int wl = (f.W + (1 << level) - 1) >> level;
   const int hl = (f.H + (1 << level) - 1) >> level;
-  const int g = (wl * hl + kTrackBlock - 1) / kTrackBlock;
-  return g < 1 ? 1 : (g > kTrackMaxGroups ? kTrackMaxGroups : g);
-}
-
-template <int DF, int STORAGE>
-static void track_launch(const MapDev& m, const FrameDev& f, const uint8_t* mask, double* pose, const TrackArgs& a,
-                         rf_track_stats* stats, double* out29, hipStream_t s) {
-  track_kernel<DF, STORAGE><<<track_grid(f, a.level), kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats, out29);
+  return ((wl + kTileW - 1) / kTileW) * ((hl + 15) >> 4);
 }
 
 static void track_dispatch(const MapDev& m, const FrameDev& f, int df, int st, const uint8_t* mask, double* pose,
-                           const TrackArgs& a, rf_track_stats* stats, double* out29, hipStream_t s) {
+                           const TrackArgs& a, rf_track_stats* stats, hipStream_t s) {
+  const int g = track_grid(f, a.level);
   if (df == RF_DEPTH_U16) {
-    if (st == RF_STORAGE_FP32) track_launch<RF_DEPTH_U16, RF_STORAGE_FP32>(m, f, mask, pose, a, stats, out29, s);
-    else track_launch<RF_DEPTH_U16, RF_STORAGE_FP16_U8>(m, f, mask, pose, a, stats, out29, s);
+    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
+    else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
   } else {
-    if (st == RF_STORAGE_FP32) track_launch<RF_DEPTH_F32, RF_STORAGE_FP32>(m, f, mask, pose, a, stats, out29, s);
-    else track_launch<RF_DEPTH_F32, RF_STORAGE_FP16_U8>(m, f, mask, pose, a, stats, out29, s);
+    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
+    else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
   }
 }
 
 void launch_track(const MapDev& m, const FrameDev& f, int df, int st, const rf_track_params& tp,
                   const uint8_t* mask, double* pose, rf_track_stats* stats, hipStream_t s) {
-  track_reset_kernel<<<1, 64, 0, s>>>(m, stats);
+  track_reset_kernel<<<1, 256, 0, s>>>(m, stats);
+  int j = 0, prev_level = -1, prev_first = 0;
   for (int l = tp.levels - 1; l >= 0; --l)
-    for (int it = 0; it < tp.iters_per_level; ++it) {
-      TrackArgs a{l, tp.w_c, tp.min_valid, tp.lm_lambda, it == 0 ? 1 : 0, 0};
-      track_dispatch(m, f, df, st, mask, pose, a, stats, nullptr, s);
+    for (int it = 0; it < tp.iters_per_level; ++it, ++j) {
+      TrackArgs a{};
+      a.level = l;
+      a.w_c = tp.w_c;
+      a.min_valid = tp.min_valid;
+      a.lm_lambda = tp.lm_lambda;
+      a.solve = j > 0;
+      a.prev_level = prev_level;
+      a.prev_first = prev_first;
+      a.acc_read = j > 0 ? (j - 1) % 3 : -1;
+      a.acc_write = j % 3;
+      a.acc_clear = j > 0 ? (j + 1) % 3 : -1;
+      a.pose_read = j > 0 ? (j - 1) % 2 : 2;
+      a.pose_write = j % 2;
+      a.mode = 0;
+      track_dispatch(m, f, df, st, mask, pose, a, stats, s);
+      prev_level = l;
+      prev_first = it == 0;
     }
+  if (j == 0) return;
+  TrackArgs a{};
+  a.level = -1;
+  a.min_valid = tp.min_valid;
+  a.lm_lambda = tp.lm_lambda;
+  a.solve = 1;
+  a.prev_level = prev_level;
+  a.prev_first = prev_first;
+  a.acc_read = (j - 1) % 3;
+  a.acc_write = -1;
+  a.acc_clear = -1;
+  a.pose_read = (j - 1) % 2;
+  a.pose_write = 2;
+  track_finalize_kernel<<<1, 64, 0, s>>>(m, pose, a, stats, nullptr);
 }
 
 void launch_normal_equations(const MapDev& m, const FrameDev& f, int df, int st, const uint8_t* mask,
                              const double* pose, int level, float w_c, double* out29, hipStream_t s) {
-  track_reset_kernel<<<1, 64, 0, s>>>(m, nullptr);
-  TrackArgs a{level, w_c, 0, 0.0, 0, 1};
-  track_dispatch(m, f, df, st, mask, const_cast<double*>(pose), a, nullptr, out29, s);
+  track_reset_kernel<<<1, 256, 0, s>>>(m, nullptr);
+  TrackArgs a{};
+  a.level = level;
+  a.w_c = w_c;
+  a.solve = 0;
+  a.acc_read = -1;
+  a.acc_write = 0;
+  a.acc_clear = -1;
+  a.pose_read = 2;
+  a.pose_write = 0;
+  track_dispatch(m, f, df, st, mask, const_cast<double*>(pose), a, nullptr, s);
+  TrackArgs b{};
+  b.mode = 1;
+  b.acc_read = 0;
+  track_finalize_kernel<<<1, 64, 0, s>>>(m, const_cast<double*>(pose), b, nullptr, out29);
 }
 
 }  // namespace rf

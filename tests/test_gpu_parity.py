@@ -317,3 +317,43 @@ def test_full_size_static_room_teacher_forced(rf, static_seq):
     ref = o32.mask(orc_frame(seq, 2), seq.poses[2], 0.5, 0.007)
     for key in ("raw", "eroded", "filled", "final"):
         assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+
+
+def test_track_is_deterministic(rf, room):
+    """Order-independent fixed-point reduction: repeated runs are bit-identical."""
+    m, _, _ = integrate_teacher_forced(rf, room, range(2))
+    tp = rf.TrackParams(room.levels, room.iters)
+    out = []
+    for _ in range(3):
+        P = dev_pose(room.poses[1])
+        m.track(gpu_frame(rf, room, 2), P, tp)
+        out.append(P.cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_track_singular_plane_keeps_pose(rf):
+    """A textureless fronto-parallel plane leaves 3 degrees of freedom
+    unconstrained: both sides stop on the singular system and keep the pose."""
+    W, H, f = 64, 48, 60.0
+    depth = np.full((H, W), 1.0, np.float32)
+    rgb = np.full((H, W, 3), 120, np.uint8)
+    K = (f, f, (W - 1) / 2, (H - 1) / 2)
+    params = rf.MapParams(0.02, 0.06, 5.0, 1 << 14, 4096, 255, 2, "fp32", W * H)
+    m = rf.Map(params)
+    g = rf.Frame.from_numpy(depth, rgb, *K)
+    I4 = np.eye(4)
+    m.allocate(g, dev_pose(I4))
+    m.integrate(g, dev_pose(I4))
+    o = O.OracleMap(0.02, 0.06, 5.0, 255, 2)
+    fr = O.Frame(depth, rgb, *K)
+    o.allocate(fr, I4)
+    o.integrate(fr, I4)
+    T0 = O.pose_left_update(np.r_[0.003, -0.002, 0.004, 0.0, 0.0, 0.0], I4)
+    T_ref, flags, _ = o.track(fr, T0, 2, 5)
+    assert flags & 2 and np.array_equal(T_ref, T0)
+    P = dev_pose(T0)
+    stats = torch.zeros(16, dtype=torch.float64, device="cuda")
+    m.track(g, P, rf.TrackParams(2, 5), None, stats)
+    iters, fl = track_stats(stats)
+    assert fl & rf.RF_FLAG_TRACK_SINGULAR and iters == 0
+    np.testing.assert_array_equal(P.cpu().numpy(), T0)
