@@ -93,13 +93,75 @@ def cpu_baseline(seq, budget_s=30.0):
                           "FP64 oracle + FP32 mask mirror, single thread" % done
 
 
+def serving_bench(args):
+    """64 concurrent sessions over the dynamic-room generator, mixed
+    resolutions, Poisson arrivals at 30 fps, FP16+u8 storage, HBM-budget
+    admission; continuous batching (paper_1905_02082_amd.serving)."""
+    import numpy as np
+    import torch
+
+    import paper_1905_02082_amd as rf
+    import synth
+    from paper_1905_02082_amd import serving
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(1905020825)
+    res = [(320, 240), (640, 480), (1280, 720)]
+    probs = [0.3, 0.5, 0.2]
+    n_sess = args.sessions
+    t0 = time.perf_counter()
+    seqs = {}
+    for (w, h) in res:
+        seqs[(w, h)] = [synth.dynamic_room(n_frames=args.serve_src_frames, width=w, height=h,
+                                           seed=1905020825 + 17 * i + w) for i in range(2)]
+    log("rendered serving sources in %.1f s" % (time.perf_counter() - t0))
+    specs = []
+    for sid in range(n_sess):
+        w, h = res[rng.choice(3, p=probs)]
+        seq = seqs[(w, h)][rng.integers(2)]
+        n = int(rng.integers(300, 2001) * args.serve_scale)
+        n = max(n, 2)
+        start = 0.0 if args.unpaced else float(rng.uniform(0.0, 2.0))
+        arr = (np.full(n, start) if args.unpaced else serving.poisson_arrivals(n, start, 30.0, rng))
+        params = rf.MapParams(seq.voxel_size, seq.truncation, seq.depth_max, 1 << 20, 1 << 17, 255,
+                              seq.carve_stride, args.storage if args.storage else "fp16", w * h)
+        specs.append(serving.SessionSpec(sid, seq, serving.ping_pong(seq.n, n), arr, params))
+    tp = rf.TrackParams(3, 10, 0.025, 64, 0.0)
+    mp = rf.MaskParams(0.5, 0.007)
+    budget = int(args.hbm_budget_gib * 2**30)
+    r = serving.serve(specs, tp, mp, budget, max_batch=args.max_batch, depth=2, device=dev,
+                      progress=lambda st, c, t: log("serving: step %d, %d/%d frames" % (st, c, t)))
+    summ = r.summary()
+    out = {"metric": "aggregate frames/s of %d concurrent mixed-resolution sessions; p50/p99 frame latency"
+                     % n_sess,
+           "value": summ["frames_per_s"], "unit": "frames/s", "n_gpus": 1, "steps": summ["steps"],
+           "warmup": 0, "ms_per_step": round(1000.0 * summ["wall_s"] / max(summ["steps"], 1), 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "serving: %d sessions, 30%% 320x240 / 50%% 640x480 / 20%% 1280x720, "
+                                  "%s arrivals, lengths U[300,2000] x %.3g frames, %s storage, HBM budget %.1f GiB, "
+                                  "max batch %d" % (n_sess, "unpaced" if args.unpaced else "Poisson 30 fps",
+                                                    args.serve_scale, args.storage or "fp16",
+                                                    args.hbm_budget_gib, args.max_batch)},
+           "latency_ms": summ["latency_ms"], "serving": summ}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=280, help="timed frames")
     ap.add_argument("--warmup", type=int, default=20, help="untimed frames before the timed region")
-    ap.add_argument("--workload", default="static_room", choices=["static_room", "dynamic_room", "large_rooms"])
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--workload", default="static_room",
+                    choices=["static_room", "dynamic_room", "large_rooms", "serving"])
+    ap.add_argument("--storage", default=None, choices=["fp32", "fp16"],
+                    help="voxel storage (default fp32; serving default fp16)")
+    ap.add_argument("--sessions", type=int, default=64, help="serving: concurrent sessions")
+    ap.add_argument("--serve-scale", type=float, default=1.0, help="serving: scale of session lengths")
+    ap.add_argument("--serve-src-frames", type=int, default=40, help="serving: rendered frames per source")
+    ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="serving: admission budget")
+    ap.add_argument("--max-batch", type=int, default=64, help="serving: sessions per step")
+    ap.add_argument("--unpaced", action="store_true", help="serving: all frames available at once")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for cpu_baseline")
     args = ap.parse_args()
@@ -117,6 +179,11 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.workload == "serving":
+        serving_bench(args)
+        return
+    if args.storage is None:
+        args.storage = "fp32"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     W, K = args.warmup, args.steps

@@ -18,8 +18,7 @@
  *    host memory.  The caller owns every buffer; the library keeps no pointer
  *    past the call except the map arena (until hashmap_destroy).
  *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Calls
- *    only enqueue work; nothing synchronises except map_status,
- *    hashmap_export's count query and rf_device_sync.
+ *    only enqueue work; only map_status synchronises (the stream).
  *  - Poses are row-major 4x4 float64 matrices, camera -> world
  *    (y_world = R x_cam + t), stored in device memory (16 doubles).
  *  - Images are row-major, width fastest.  Depth: uint16 (x depth_scale
@@ -213,6 +212,31 @@ rf_status hashmap_export(rf_map* m, int32_t* d_keys, float* d_sdf, float* d_weig
  * storage rounds sdf/tau to nearest even. */
 rf_status hashmap_import(rf_map* m, const int32_t* d_keys, const float* d_sdf, const float* d_weight,
                          const uint8_t* d_rgb, uint32_t n, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched forms (many sessions, one launch per stage).  Each job names its
+ * own map, frame, device pose and buffers; a map may appear at most once per
+ * call.  A job's results are identical (bit for bit) to the single-map call:
+ * jobs share launches, never state.  Jobs are grouped internally by depth
+ * format and storage and issued in launches of up to 8 jobs, in order.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  rf_map* map;
+  rf_frame frame;
+  double* d_pose;           /* device 4x4 float64: in/out for tracking, read otherwise */
+  const uint8_t* d_mask;    /* nullable input mask (registration pass 2, allocation, integration) */
+  uint8_t* d_mask_out;      /* compute_dynamic_mask_batch output (width*height uint8) */
+  rf_track_stats* d_stats;  /* nullable, track_frame_batch only */
+} rf_job;
+
+/* track_frame for every job (same rf_track_params for all). */
+rf_status track_frame_batch(const rf_job* jobs, int32_t n, const rf_track_params* tp, void* stream);
+/* compute_dynamic_mask for every job (writes d_mask_out). */
+rf_status compute_dynamic_mask_batch(const rf_job* jobs, int32_t n, const rf_mask_params* mp, void* stream);
+/* hashmap_allocate for every job (uses d_pose, d_mask). */
+rf_status hashmap_allocate_batch(const rf_job* jobs, int32_t n, void* stream);
+/* integrate_frame for every job (uses d_pose, d_mask); follows hashmap_allocate_batch. */
+rf_status integrate_frame_batch(const rf_job* jobs, int32_t n, void* stream);
 
 /* Thread-local description of the last error returned on this thread. */
 const char* rf_last_error(void);

@@ -20,8 +20,8 @@ from ._native import (RF_DEPTH_F32, RF_DEPTH_U16, RF_FLAG_HASH_FULL, RF_FLAG_MAS
                       RF_FLAG_POOL_FULL, RF_FLAG_TRACK_FEW_PIXELS, RF_FLAG_TRACK_SINGULAR,
                       RF_STORAGE_FP16_U8, RF_STORAGE_FP32)
 
-__all__ = ["MapParams", "TrackParams", "MaskParams", "Frame", "Map", "Pipeline", "RefusionError",
-           "hashmap_bytes", "lib"]
+__all__ = ["MapParams", "TrackParams", "MaskParams", "Frame", "Map", "Session", "Pipeline", "process_batch",
+           "RefusionError", "hashmap_bytes", "lib"]
 
 
 class RefusionError(RuntimeError):
@@ -290,40 +290,97 @@ class Map:
         return tuple(int(v[i].item()) for i in range(6, 10))
 
 
-class Pipeline:
-    """The per-frame method on one map with device-resident pose and mask.
+class Session:
+    """One reconstruction session: a map plus its device-resident pose, mask
+    and tracking statistics.  Frames advance through process_batch."""
 
-    process(frame) runs: first frame -> allocate + integrate at the initial
-    pose; later frames -> track (no mask), dynamic mask, track (masked),
-    allocate, integrate (all enqueued on the current stream, no host sync).
-    """
-
-    def __init__(self, params: MapParams, tp: TrackParams, mp: MaskParams, initial_pose, dynamic=True,
-                 device="cuda"):
+    def __init__(self, params: MapParams, initial_pose, device="cuda"):
         self.map = Map(params, device)
-        self.tp, self.mp = tp, mp
-        self.dynamic = dynamic
         self.pose = torch.as_tensor(initial_pose, dtype=torch.float64).to(device).contiguous()
         self.mask = None
         self.stats = torch.zeros(16, dtype=torch.float64, device=device)
         self.k = 0
 
+    def _mask_for(self, frame):
+        if self.mask is None or tuple(self.mask.shape) != (frame.H, frame.W):
+            self.mask = torch.empty((frame.H, frame.W), dtype=torch.uint8, device=self.pose.device)
+        return self.mask
+
+
+def _jobs(sessions, frames, mask=False, mask_out=False, stats=False):
+    arr = (N.RfJob * len(sessions))()
+    for i, (s, f) in enumerate(zip(sessions, frames)):
+        j = arr[i]
+        j.map = s.map.h
+        j.frame = f.s
+        j.d_pose = s.pose.data_ptr()
+        j.d_mask = s.mask.data_ptr() if (mask and s.mask is not None) else None
+        j.d_mask_out = s._mask_for(f).data_ptr() if mask_out else None
+        j.d_stats = s.stats.data_ptr() if stats else None
+    return arr
+
+
+def process_batch(sessions, frames, tp: TrackParams, mp: MaskParams, dynamic=True, stream=None):
+    """One step of the method for several sessions at once (one frame each),
+    one launch set per stage (the paper's Fig. 2 order):
+
+        registration without mask -> dynamic mask -> registration with mask
+        -> block allocation -> integration
+
+    A session's first frame is only allocated and integrated at its initial
+    pose.  Every result is the same as processing the session alone."""
+    if len(sessions) != len(frames):
+        raise RefusionError("one frame per session")
+    L = N.load()
+    st = _stream(stream)
+    run = [i for i, s in enumerate(sessions) if s.k > 0]
+    if run:
+        rs = [sessions[i] for i in run]
+        rf_ = [frames[i] for i in run]
+        tpc = tp.c()
+        _check(L.track_frame_batch(_jobs(rs, rf_, stats=True), len(rs), ctypes.byref(tpc), st), "track_frame_batch")
+        if dynamic:
+            mpc = mp.c()
+            _check(L.compute_dynamic_mask_batch(_jobs(rs, rf_, mask_out=True), len(rs), ctypes.byref(mpc), st),
+                   "compute_dynamic_mask_batch")
+            _check(L.track_frame_batch(_jobs(rs, rf_, mask=True, stats=True), len(rs), ctypes.byref(tpc), st),
+                   "track_frame_batch")
+    use_mask = [dynamic and s.k > 0 for s in sessions]
+    jobs = _jobs(sessions, frames)
+    for i, s in enumerate(sessions):
+        jobs[i].d_mask = s.mask.data_ptr() if (use_mask[i] and s.mask is not None) else None
+    _check(L.hashmap_allocate_batch(jobs, len(sessions), st), "hashmap_allocate_batch")
+    _check(L.integrate_frame_batch(jobs, len(sessions), st), "integrate_frame_batch")
+    for s in sessions:
+        s.k += 1
+
+
+class Pipeline:
+    """The per-frame method on one map with device-resident pose and mask
+    (process_batch with a single session)."""
+
+    def __init__(self, params: MapParams, tp: TrackParams, mp: MaskParams, initial_pose, dynamic=True,
+                 device="cuda"):
+        self.session = Session(params, initial_pose, device)
+        self.tp, self.mp = tp, mp
+        self.dynamic = dynamic
+
+    @property
+    def map(self):
+        return self.session.map
+
+    @property
+    def pose(self):
+        return self.session.pose
+
+    @property
+    def mask(self):
+        return self.session.mask
+
+    @property
+    def stats(self):
+        return self.session.stats
+
     def process(self, frame: Frame, stream=None):
-        m = self.map
-        if self.k == 0:
-            m.allocate(frame, self.pose, None, stream)
-            m.integrate(frame, self.pose, None, stream)
-            self.k += 1
-            return self.pose
-        m.track(frame, self.pose, self.tp, None, self.stats, stream)
-        mask = None
-        if self.dynamic:
-            if self.mask is None or tuple(self.mask.shape) != (frame.H, frame.W):
-                self.mask = torch.empty((frame.H, frame.W), dtype=torch.uint8, device=self.pose.device)
-            m.dynamic_mask(frame, self.pose, self.mp, out=self.mask, stream=stream)
-            mask = self.mask
-            m.track(frame, self.pose, self.tp, mask, self.stats, stream)
-        m.allocate(frame, self.pose, mask, stream)
-        m.integrate(frame, self.pose, mask, stream)
-        self.k += 1
-        return self.pose
+        process_batch([self.session], [frame], self.tp, self.mp, self.dynamic, stream)
+        return self.session.pose

@@ -50,6 +50,11 @@ class RfTrackStats(ctypes.Structure):
                 ("level_count", c_double * 8)]
 
 
+class RfJob(ctypes.Structure):
+    _fields_ = [("map", c_void_p), ("frame", RfFrame), ("d_pose", c_void_p), ("d_mask", c_void_p),
+                ("d_mask_out", c_void_p), ("d_stats", c_void_p)]
+
+
 EXPORTS = {
     "hashmap_bytes": (c_int32, [ctypes.POINTER(RfMapParams), ctypes.POINTER(c_size_t)]),
     "hashmap_create": (c_int32, [ctypes.POINTER(RfMapParams), c_void_p, c_size_t, c_void_p,
@@ -73,6 +78,11 @@ EXPORTS = {
     "hashmap_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p,
                                  c_void_p]),
     "hashmap_import": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p]),
+    "track_frame_batch": (c_int32, [ctypes.POINTER(RfJob), c_int32, ctypes.POINTER(RfTrackParams), c_void_p]),
+    "compute_dynamic_mask_batch": (c_int32, [ctypes.POINTER(RfJob), c_int32, ctypes.POINTER(RfMaskParams),
+                                             c_void_p]),
+    "hashmap_allocate_batch": (c_int32, [ctypes.POINTER(RfJob), c_int32, c_void_p]),
+    "integrate_frame_batch": (c_int32, [ctypes.POINTER(RfJob), c_int32, c_void_p]),
     "rf_last_error": (ctypes.c_char_p, []),
     "rf_version": (ctypes.c_char_p, []),
 }

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "rf_device.h"
 #include "rf_internal.h"
@@ -96,6 +97,64 @@ rf_status make_frame(const rf_frame* f, rf::FrameDev& out) {
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+rf::Job base_job(rf_map* m, const rf::FrameDev& fd) {
+  rf::Job J{};
+  J.m = m->h.dev;
+  J.f = fd;
+  return J;
+}
+
+// Validates a job list and runs `launch` on chunks of at most kMaxBatch jobs
+// that share depth format and storage (the kernels' template parameters).
+template <class Fill, class Launch>
+rf_status run_batches(const rf_job* jobs, int32_t n, const char* what, Fill fill, Launch launch) {
+  if (n < 0 || (n > 0 && !jobs)) return fail(RF_EINVAL, "%s: bad job list", what);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!jobs[i].map || !jobs[i].d_pose) return fail(RF_EINVAL, "%s: job %d has no map or pose", what, i);
+    rf::FrameDev fd;
+    rf_status st = make_frame(&jobs[i].frame, fd);
+    if (st) return st;
+    for (int32_t k = 0; k < i; ++k)
+      if (jobs[k].map == jobs[i].map) return fail(RF_EINVAL, "%s: map of job %d appears twice", what, i);
+  }
+  std::vector<int> done(n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    if (done[i]) continue;
+    const int df = jobs[i].frame.depth_format, sto = jobs[i].map->h.p.storage;
+    rf::Batch b{};
+    b.n = 0;
+    for (int32_t k = i; k < n; ++k) {
+      if (done[k] || jobs[k].frame.depth_format != df || jobs[k].map->h.p.storage != sto) continue;
+      rf::FrameDev fd;
+      make_frame(&jobs[k].frame, fd);
+      rf::Job J = base_job(jobs[k].map, fd);
+      rf_status st = fill(jobs[k], J);
+      if (st) return st;
+      b.job[b.n++] = J;
+      done[k] = 1;
+      if (b.n == rf::kMaxBatch) {
+        launch(b, df, sto);
+        b.n = 0;
+      }
+    }
+    if (b.n) launch(b, df, sto);
+  }
+  return check_launch(what);
+}
+
+rf_status mask_checks(const rf_job& j, rf::Job& J) {
+  if (!j.d_mask_out) return fail(RF_EINVAL, "compute_dynamic_mask: mask output is NULL");
+  const uint32_t npx = (uint32_t)J.f.W * (uint32_t)J.f.H;
+  if (npx > j.map->h.p.max_pixels)
+    return fail(RF_ENOMEM, "frame has %u pixels, map max_pixels is %u", npx, j.map->h.p.max_pixels);
+  const uint32_t tiles =
+      (uint32_t)((J.f.W + rf::kTile - 1) / rf::kTile) * (uint32_t)((J.f.H + rf::kTile - 1) / rf::kTile);
+  if (tiles > j.map->h.dev.dirty_cap) return fail(RF_ENOMEM, "flood-fill tile table too small");
+  J.pose = j.d_pose;
+  J.mask_out = j.d_mask_out;
+  return RF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,36 +233,35 @@ rf_status hashmap_reset(rf_map* m, void* stream) {
 }
 
 rf_status hashmap_allocate(rf_map* m, const rf_frame* f, const double* d_pose, const uint8_t* d_mask, void* stream) {
-  if (!m || !d_pose) return fail(RF_EINVAL, "map/pose is NULL");
-  rf::FrameDev fd;
-  rf_status st = make_frame(f, fd);
-  if (st) return st;
-  // frame stamps: 0 is the initial bucket value, so the epoch skips 0 on wrap
-  m->h.frame_id = (m->h.frame_id == 0xFFFFFFFFu) ? 1u : m->h.frame_id + 1u;
-  rf::launch_allocate(m->h.dev, fd, f->depth_format, d_pose, d_mask, m->h.frame_id, S(stream));
-  return check_launch("hashmap_allocate");
+  if (!m || !d_pose || !f) return fail(RF_EINVAL, "map/pose/frame is NULL");
+  rf_job j{};
+  j.map = m;
+  j.frame = *f;
+  j.d_pose = const_cast<double*>(d_pose);
+  j.d_mask = d_mask;
+  return hashmap_allocate_batch(&j, 1, stream);
 }
 
 rf_status integrate_frame(rf_map* m, const rf_frame* f, const double* d_pose, const uint8_t* d_mask, void* stream) {
-  if (!m || !d_pose) return fail(RF_EINVAL, "map/pose is NULL");
-  rf::FrameDev fd;
-  rf_status st = make_frame(f, fd);
-  if (st) return st;
-  rf::launch_integrate(m->h.dev, fd, f->depth_format, m->h.p.storage, d_pose, d_mask, S(stream));
-  return check_launch("integrate_frame");
+  if (!m || !d_pose || !f) return fail(RF_EINVAL, "map/pose/frame is NULL");
+  rf_job j{};
+  j.map = m;
+  j.frame = *f;
+  j.d_pose = const_cast<double*>(d_pose);
+  j.d_mask = d_mask;
+  return integrate_frame_batch(&j, 1, stream);
 }
 
 rf_status track_frame(rf_map* m, const rf_frame* f, const rf_track_params* tp, const uint8_t* d_mask,
                       double* d_pose_inout, rf_track_stats* d_stats, void* stream) {
-  if (!m || !tp || !d_pose_inout) return fail(RF_EINVAL, "map/params/pose is NULL");
-  if (tp->levels < 1 || tp->levels > 8 || tp->iters_per_level < 0 || tp->iters_per_level > 1000)
-    return fail(RF_EINVAL, "levels must be in [1,8], iters_per_level in [0,1000]");
-  if (!(tp->lm_lambda >= 0.0)) return fail(RF_EINVAL, "lm_lambda must be >= 0");
-  rf::FrameDev fd;
-  rf_status st = make_frame(f, fd);
-  if (st) return st;
-  rf::launch_track(m->h.dev, fd, f->depth_format, m->h.p.storage, *tp, d_mask, d_pose_inout, d_stats, S(stream));
-  return check_launch("track_frame");
+  if (!m || !tp || !d_pose_inout || !f) return fail(RF_EINVAL, "map/params/pose/frame is NULL");
+  rf_job j{};
+  j.map = m;
+  j.frame = *f;
+  j.d_pose = d_pose_inout;
+  j.d_mask = d_mask;
+  j.d_stats = d_stats;
+  return track_frame_batch(&j, 1, tp, stream);
 }
 
 rf_status track_normal_equations(rf_map* m, const rf_frame* f, const uint8_t* d_mask, const double* d_pose,
@@ -213,31 +271,92 @@ rf_status track_normal_equations(rf_map* m, const rf_frame* f, const uint8_t* d_
   rf::FrameDev fd;
   rf_status st = make_frame(f, fd);
   if (st) return st;
-  rf::launch_normal_equations(m->h.dev, fd, f->depth_format, m->h.p.storage, d_mask, d_pose, level, w_c, d_out29,
-                              S(stream));
+  rf::Batch b{};
+  b.n = 1;
+  b.job[0] = base_job(m, fd);
+  b.job[0].mask = d_mask;
+  b.job[0].pose = const_cast<double*>(d_pose);
+  rf::launch_normal_equations(b, f->depth_format, m->h.p.storage, level, w_c, d_out29, S(stream));
   return check_launch("track_normal_equations");
 }
 
 rf_status compute_dynamic_mask_stages(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
                                       uint8_t* d_raw, uint8_t* d_eroded, uint8_t* d_filled, uint8_t* d_mask_out,
                                       float* d_residual_out, void* stream) {
-  if (!m || !d_pose || !mp || !d_mask_out) return fail(RF_EINVAL, "map/pose/params/out is NULL");
+  if (!m || !d_pose || !mp || !d_mask_out || !f) return fail(RF_EINVAL, "map/pose/params/out/frame is NULL");
   if (!(mp->gamma >= 0.0f) || !(mp->theta >= 0.0f)) return fail(RF_EINVAL, "gamma and theta must be >= 0");
+  rf_job j{};
+  j.map = m;
+  j.frame = *f;
+  j.d_pose = const_cast<double*>(d_pose);
+  j.d_mask_out = d_mask_out;
   rf::FrameDev fd;
   rf_status st = make_frame(f, fd);
   if (st) return st;
-  const uint32_t npx = (uint32_t)fd.W * (uint32_t)fd.H;
-  if (npx > m->h.p.max_pixels) return fail(RF_ENOMEM, "frame has %u pixels, map max_pixels is %u", npx, m->h.p.max_pixels);
-  const uint32_t tiles = (uint32_t)((fd.W + rf::kTile - 1) / rf::kTile) * (uint32_t)((fd.H + rf::kTile - 1) / rf::kTile);
-  if (tiles > m->h.dev.dirty_cap) return fail(RF_ENOMEM, "flood-fill tile table too small");
-  rf::launch_mask(m->h.dev, fd, f->depth_format, m->h.p.storage, d_pose, *mp, d_raw, d_eroded, d_filled, d_mask_out,
-                  d_residual_out, S(stream));
-  return check_launch("compute_dynamic_mask");
+  auto fill = [&](const rf_job& jj, rf::Job& J) -> rf_status {
+    rf_status s2 = mask_checks(jj, J);
+    if (s2) return s2;
+    J.raw = d_raw;
+    J.eroded = d_eroded;
+    J.filled = d_filled;
+    J.residual = d_residual_out;
+    return RF_OK;
+  };
+  auto launch = [&](rf::Batch& b, int df, int sto) { rf::launch_mask(b, df, sto, *mp, S(stream)); };
+  return run_batches(&j, 1, "compute_dynamic_mask", fill, launch);
 }
 
 rf_status compute_dynamic_mask(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
                                uint8_t* d_mask_out, float* d_residual_out, void* stream) {
   return compute_dynamic_mask_stages(m, f, d_pose, mp, nullptr, nullptr, nullptr, d_mask_out, d_residual_out, stream);
+}
+
+// ---------------------------------------------------------------- batched entry points
+rf_status hashmap_allocate_batch(const rf_job* jobs, int32_t n, void* stream) {
+  auto fill = [&](const rf_job& j, rf::Job& J) -> rf_status {
+    rf::HostMap& h = j.map->h;
+    // frame stamps: 0 is the initial bucket value, so the epoch skips 0 on wrap
+    h.frame_id = (h.frame_id == 0xFFFFFFFFu) ? 1u : h.frame_id + 1u;
+    J.frame_id = h.frame_id;
+    J.pose = j.d_pose;
+    J.mask = j.d_mask;
+    return RF_OK;
+  };
+  auto launch = [&](rf::Batch& b, int df, int) { rf::launch_allocate(b, df, S(stream)); };
+  return run_batches(jobs, n, "hashmap_allocate", fill, launch);
+}
+
+rf_status integrate_frame_batch(const rf_job* jobs, int32_t n, void* stream) {
+  auto fill = [&](const rf_job& j, rf::Job& J) -> rf_status {
+    J.pose = j.d_pose;
+    J.mask = j.d_mask;
+    return RF_OK;
+  };
+  auto launch = [&](rf::Batch& b, int df, int sto) { rf::launch_integrate(b, df, sto, S(stream)); };
+  return run_batches(jobs, n, "integrate_frame", fill, launch);
+}
+
+rf_status track_frame_batch(const rf_job* jobs, int32_t n, const rf_track_params* tp, void* stream) {
+  if (!tp) return fail(RF_EINVAL, "track params are NULL");
+  if (tp->levels < 1 || tp->levels > 8 || tp->iters_per_level < 0 || tp->iters_per_level > 1000)
+    return fail(RF_EINVAL, "levels must be in [1,8], iters_per_level in [0,1000]");
+  if (!(tp->lm_lambda >= 0.0)) return fail(RF_EINVAL, "lm_lambda must be >= 0");
+  auto fill = [&](const rf_job& j, rf::Job& J) -> rf_status {
+    J.pose = j.d_pose;
+    J.mask = j.d_mask;
+    J.stats = j.d_stats;
+    return RF_OK;
+  };
+  auto launch = [&](rf::Batch& b, int df, int sto) { rf::launch_track(b, df, sto, *tp, S(stream)); };
+  return run_batches(jobs, n, "track_frame", fill, launch);
+}
+
+rf_status compute_dynamic_mask_batch(const rf_job* jobs, int32_t n, const rf_mask_params* mp, void* stream) {
+  if (!mp) return fail(RF_EINVAL, "mask params are NULL");
+  if (!(mp->gamma >= 0.0f) || !(mp->theta >= 0.0f)) return fail(RF_EINVAL, "gamma and theta must be >= 0");
+  auto fill = [&](const rf_job& j, rf::Job& J) -> rf_status { return mask_checks(j, J); };
+  auto launch = [&](rf::Batch& b, int df, int sto) { rf::launch_mask(b, df, sto, *mp, S(stream)); };
+  return run_batches(jobs, n, "compute_dynamic_mask", fill, launch);
 }
 
 rf_status extract_surface(rf_map* m, float* d_points, uint32_t cap, uint32_t* d_count, void* stream) {

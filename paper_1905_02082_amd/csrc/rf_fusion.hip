@@ -4,45 +4,62 @@
 // Allocation: one thread per pixel walks the block grid along its band (or
 // carve) segment with a DDA; each visited block is inserted into the hash by
 // CAS and, the first time it is touched in this frame (per-bucket frame
-// stamp, exchanged atomically), appended to the frame's block list.
+// stamp, exchanged atomically), appended to the frame's block list.  Carve
+// rays run in workgroups of their own; cells are probed 8 at a time.
 //
-// Integration: one workgroup per listed block, 256 threads x 2 voxels; the
-// keep/skip decision needs only the frame, so a voxel's record is read and
-// written only when it is updated (occluded, masked and out-of-view voxels
-// cost no HBM traffic).  Records are SoA per block, so a workgroup's loads
-// and stores are contiguous 2-KiB (FP32) / 1-KiB (FP16) runs.
+// Integration: one workgroup per listed block, one voxel per thread; a
+// voxel's record is written only when it is updated (occluded, masked and
+// out-of-view voxels are never stored).  Records are SoA per block, so a
+// workgroup's loads and stores are contiguous 4-KiB (FP32) / 2-KiB (FP16)
+// runs.
 #include "rf_device.h"
 #include "rf_internal.h"
 
 namespace rf {
 
-// Visit the block cells of segment q0 -> q1 (block units): exactly |e-c|_1
-// steps, each along the axis with the smallest next-boundary parameter among
-// the axes not yet at the end cell (ties: x, y, z).
-template <typename Visit>
-__device__ __forceinline__ void dda_blocks(const float q0[3], const float q1[3], Visit&& visit) {
+// Records a block of the frame: first touch this frame (stamp exchanged
+// atomically) appends its bucket to the frame list.  stamp0 is the stamp
+// value seen by the probe: equal to frame_id means already recorded.
+__device__ __forceinline__ void touch_block(const MapDev& m, int h, uint32_t stamp0, uint32_t frame_id) {
+  if (stamp0 == frame_id) return;
+  if (atomicExch(&m.buckets[h].stamp, frame_id) != frame_id) {
+    const uint32_t i = atomicAdd(&m.st->f_count, 1u);
+    if (i < m.flist_cap) m.flist[i] = (uint32_t)h;
+  }
+}
+
+// Block-grid DDA of segment q0 -> q1 (block units): cells c = floor(q0) ...
+// e = floor(q1), exactly |e-c|_1 steps, each along the axis with the smallest
+// next-boundary parameter among the axes not yet at e (ties: x, y, z).  Cells
+// are produced in batches of 8 whose home buckets are loaded together, so a
+// ray costs one hash round trip per 8 cells instead of one per cell.
+struct Dda {
   int c[3], e[3], step[3];
   float tmax[3], tdel[3];
-  int n = 0;
+  int left;  // cells still to emit, the current one included
+
+  __device__ __forceinline__ void init(const float q0[3], const float q1[3]) {
+    int n = 0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    c[a] = (int)floorf(q0[a]);
-    e[a] = (int)floorf(q1[a]);
-    const float d = q1[a] - q0[a];
-    step[a] = (e[a] > c[a]) ? 1 : ((e[a] < c[a]) ? -1 : 0);
-    if (step[a] != 0) {
-      const float inv = 1.0f / d;
-      const float bound = (float)(c[a] + (step[a] > 0 ? 1 : 0));
-      tmax[a] = (bound - q0[a]) * inv;
-      tdel[a] = (float)step[a] * inv;
-    } else {
-      tmax[a] = INFINITY;
-      tdel[a] = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+      c[a] = (int)floorf(q0[a]);
+      e[a] = (int)floorf(q1[a]);
+      const float d = q1[a] - q0[a];
+      step[a] = (e[a] > c[a]) ? 1 : ((e[a] < c[a]) ? -1 : 0);
+      if (step[a] != 0) {
+        const float inv = 1.0f / d;
+        const float bound = (float)(c[a] + (step[a] > 0 ? 1 : 0));
+        tmax[a] = (bound - q0[a]) * inv;
+        tdel[a] = (float)step[a] * inv;
+      } else {
+        tmax[a] = INFINITY;
+        tdel[a] = INFINITY;
+      }
+      n += abs(e[a] - c[a]);
     }
-    n += abs(e[a] - c[a]);
+    left = n + 1;
   }
-  visit(c);
-  for (int k = 0; k < n; ++k) {
+  __device__ __forceinline__ void advance() {
     int best = -1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -51,22 +68,44 @@ __device__ __forceinline__ void dda_blocks(const float q0[3], const float q1[3],
     }
     c[best] += step[best];
     tmax[best] += tdel[best];
-    visit(c);
   }
-}
+};
 
 template <int DF>
-__global__ __launch_bounds__(256) void alloc_kernel(MapDev m, FrameDev f, const double* __restrict__ pose,
-                                                    const uint8_t* __restrict__ mask, uint32_t frame_id) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= f.W * f.H) return;
-  const int u = idx % f.W, v = idx / f.W;
+__global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
+  // Per job: workgroups [0, band_groups) take the band segments of the pixels
+  // that are not on the carve grid; the rest take the carve segments of the
+  // carve-grid pixels, so the long rays share wavefronts with rays of similar
+  // length.
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  const FrameDev& f = J.f;
+  const int g = blockIdx.x - b.base[jb];
+  int u, v;
+  const int s_c = (int)m.carve_stride;
+  if (g < J.band_groups) {
+    const int idx = g * blockDim.x + threadIdx.x;
+    if (idx >= f.W * f.H) return;
+    u = idx % f.W;
+    v = idx / f.W;
+    if (u % s_c == 0 && v % s_c == 0) return;
+  } else {
+    const int j = (g - J.band_groups) * blockDim.x + threadIdx.x;
+    if (j >= J.carve_w * J.carve_h) return;
+    u = (j % J.carve_w) * s_c;
+    v = (j / J.carve_w) * s_c;
+  }
+  const uint8_t* mask = J.mask;
+  const double* pose = J.pose;
+  const uint32_t frame_id = J.frame_id;
+  const int idx = v * f.W + u;
   const float D = load_depth<DF>(f, idx);
   if (!depth_ok(D, m.dmax)) return;
   if (mask && mask[idx]) return;
   float R[9], t[3];
   load_pose_f(pose, R, t);
-  const bool carve = (u % (int)m.carve_stride == 0) && (v % (int)m.carve_stride == 0);
+  const bool carve = (u % s_c == 0) && (v % s_c == 0);
   const float zn = carve ? 0.0f : fmaxf(D - m.tau, 0.0f);
   const float zf = D + m.tau;
   const float rx = ((float)u - f.cx) * f.ifx, ry = ((float)v - f.cy) * f.ify;
@@ -81,78 +120,114 @@ __global__ __launch_bounds__(256) void alloc_kernel(MapDev m, FrameDev f, const 
     q1[a] = P1[a] * m.iB;
     if (!(fabsf(q0[a]) < kMaxBlockCoord && fabsf(q1[a]) < kMaxBlockCoord)) return;
   }
-  dda_blocks(q0, q1, [&](const int* c) {
-    const int h = insert_block(m, c[0], c[1], c[2]);
-    if (h < 0) return;
-    uint32_t* stamp = &m.buckets[h].stamp;
-    if (*stamp != frame_id) {
-      if (atomicExch(stamp, frame_id) != frame_id) {
-        const uint32_t i = atomicAdd(&m.st->f_count, 1u);
-        if (i < m.flist_cap) m.flist[i] = (uint32_t)h;
+  Dda d;
+  d.init(q0, q1);
+  constexpr int kBatch = 8;
+  while (d.left > 0) {
+    int cx[kBatch], cy[kBatch], cz[kBatch];
+    bool ok[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      ok[q] = d.left > 0;
+      cx[q] = d.c[0];
+      cy[q] = d.c[1];
+      cz[q] = d.c[2];
+      if (ok[q]) {
+        --d.left;
+        if (d.left > 0) d.advance();
       }
     }
-  });
-}
-
-__global__ void reset_frame_list_kernel(MapDev m) {
-  if (threadIdx.x == 0) {
-    m.st->f_count = 0;
-    m.st->n_band = 0;
-    m.st->n_free = 0;
+    unsigned long long key[kBatch];
+    uint32_t hb[kBatch];
+    Bucket bk[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      if (!ok[q]) continue;
+      key[q] = pack_key(cx[q], cy[q], cz[q]);
+      hb[q] = hash3(cx[q], cy[q], cz[q]) & m.bucket_mask;
+      bk[q] = m.buckets[hb[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      if (!ok[q]) continue;
+      if (bk[q].key == key[q]) {
+        touch_block(m, (int)hb[q], bk[q].stamp, frame_id);
+      } else {
+        const int h = insert_block(m, cx[q], cy[q], cz[q]);
+        if (h >= 0) touch_block(m, h, m.buckets[h].stamp, frame_id);
+      }
+    }
   }
 }
 
-// Integration of one frame into the blocks of the frame list.
+__global__ void reset_frame_list_kernel(Batch b) {
+  if (threadIdx.x == 0 && (int)blockIdx.x < b.n) {
+    DevState* st = b.job[blockIdx.x].m.st;
+    st->f_count = 0;
+    st->n_band = 0;
+    st->n_free = 0;
+  }
+}
+
+// Integration of one frame into the blocks of the frame list: one
+// workgroup per listed block, one voxel per thread.  The voxel's sdf/weight
+// record is loaded before the keep/skip decision so that the load overlaps
+// the projection and the depth gather; it is stored only when updated.
 template <int DF, int STORAGE>
-__global__ __launch_bounds__(256) void integrate_kernel(MapDev m, FrameDev f, const double* __restrict__ pose,
-                                                        const uint8_t* __restrict__ mask) {
+__global__ __launch_bounds__(512) void integrate_kernel(Batch b) {
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  const FrameDev& f = J.f;
+  const uint8_t* mask = J.mask;
+  const double* pose = J.pose;
+  const uint32_t g0 = blockIdx.x - b.base[jb], gn = b.base[jb + 1] - b.base[jb];
   const uint32_t nF = min(m.st->f_count, m.flist_cap);
   float R[9], t[3];
   load_pose_f(pose, R, t);
   uint32_t nb = 0, nf = 0;
-  for (uint32_t fi = blockIdx.x; fi < nF; fi += gridDim.x) {
+  const int l = threadIdx.x;
+  for (uint32_t fi = g0; fi < nF; fi += gn) {
     const uint32_t h = m.flist[fi];
-    const uint32_t slot = m.buckets[h].slot;
-    if (slot >= m.max_blocks) continue;
+    const Bucket bu = m.buckets[h];
+    if (bu.slot >= m.max_blocks) continue;
     int bx, by, bz;
-    unpack_key(m.buckets[h].key, bx, by, bz);
-    for (int l = threadIdx.x; l < 512; l += blockDim.x) {
-      const int vi[3] = {8 * bx + (l & 7), 8 * by + ((l >> 3) & 7), 8 * bz + (l >> 6)};
-      float d[3], X[3];
+    unpack_key(bu.key, bx, by, bz);
+    const uint32_t vidx = bu.slot * 512u + (uint32_t)l;
+    float sdf, W;
+    VoxelStore<STORAGE>::load(m, vidx, sdf, W);
+    const int vi[3] = {8 * bx + (l & 7), 8 * by + ((l >> 3) & 7), 8 * bz + (l >> 6)};
+    float d[3], X[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) d[a] = (float)vi[a] * m.s - t[a];
+    for (int a = 0; a < 3; ++a) d[a] = (float)vi[a] * m.s - t[a];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) X[j] = (R[j] * d[0] + R[3 + j] * d[1]) + R[6 + j] * d[2];
-      if (!(X[2] > 0.0f)) continue;
-      const float uf = f.fx * (X[0] / X[2]) + f.cx;
-      const float vf = f.fy * (X[1] / X[2]) + f.cy;
-      const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
-      if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) continue;
-      const int pix = (int)vr * f.W + (int)ur;
-      const float D = load_depth<DF>(f, pix);
-      if (!depth_ok(D, m.dmax)) continue;
-      if (mask && mask[pix]) continue;
-      const float eta = D - X[2];
-      if (eta < -m.tau) continue;
-      const bool band = (eta <= m.tau);
-      if (!band && !(X[2] <= m.dmax)) continue;
-      const float dval = band ? eta : m.tau;
-      const uint32_t vidx = slot * 512u + (uint32_t)l;
-      float sdf, W;
-      VoxelStore<STORAGE>::load(m, vidx, sdf, W);
-      const float Wn = W + 1.0f;
-      VoxelStore<STORAGE>::store(m, vidx, (W * sdf + dval) / Wn, fminf(Wn, m.max_weight));
-      if (band) {
-        const uchar4 c = m.rgb[vidx];
-        const uint8_t* px = f.rgb + 3 * pix;
-        const float r = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.x + (float)px[0]) / Wn)));
-        const float g = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.y + (float)px[1]) / Wn)));
-        const float b = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.z + (float)px[2]) / Wn)));
-        m.rgb[vidx] = make_uchar4((unsigned char)r, (unsigned char)g, (unsigned char)b, 0);
-        ++nb;
-      } else {
-        ++nf;
-      }
+    for (int j = 0; j < 3; ++j) X[j] = (R[j] * d[0] + R[3 + j] * d[1]) + R[6 + j] * d[2];
+    if (!(X[2] > 0.0f)) continue;
+    const float uf = f.fx * (X[0] / X[2]) + f.cx;
+    const float vf = f.fy * (X[1] / X[2]) + f.cy;
+    const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
+    if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) continue;
+    const int pix = (int)vr * f.W + (int)ur;
+    const float D = load_depth<DF>(f, pix);
+    if (!depth_ok(D, m.dmax)) continue;
+    if (mask && mask[pix]) continue;
+    const float eta = D - X[2];
+    if (eta < -m.tau) continue;
+    const bool band = (eta <= m.tau);
+    if (!band && !(X[2] <= m.dmax)) continue;
+    const float dval = band ? eta : m.tau;
+    const float Wn = W + 1.0f;
+    VoxelStore<STORAGE>::store(m, vidx, (W * sdf + dval) / Wn, fminf(Wn, m.max_weight));
+    if (band) {
+      const uchar4 c = m.rgb[vidx];
+      const uint8_t* px = f.rgb + 3 * pix;
+      const float r = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.x + (float)px[0]) / Wn)));
+      const float g = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.y + (float)px[1]) / Wn)));
+      const float bl = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.z + (float)px[2]) / Wn)));
+      m.rgb[vidx] = make_uchar4((unsigned char)r, (unsigned char)g, (unsigned char)bl, 0);
+      ++nb;
+    } else {
+      ++nf;
     }
   }
   // per-workgroup update counts (band / free) for the roofline accounting
@@ -171,7 +246,7 @@ __global__ __launch_bounds__(256) void integrate_kernel(MapDev m, FrameDev f, co
       atomicAdd(&m.st->n_free, (unsigned long long)s_cnt[1]);
       atomicAdd(&m.st->cum_free, (unsigned long long)s_cnt[1]);
     }
-    if (blockIdx.x == 0) {
+    if (g0 == 0) {
       atomicAdd(&m.st->cum_blocks, (unsigned long long)nF);
       atomicAdd(&m.st->cum_frames, 1ull);
     }
@@ -179,32 +254,35 @@ __global__ __launch_bounds__(256) void integrate_kernel(MapDev m, FrameDev f, co
 }
 
 // ------------------------------------------------------------ host launchers
-void launch_allocate(const MapDev& m, const FrameDev& f, int depth_format, const double* pose,
-                     const uint8_t* mask, uint32_t frame_id, hipStream_t s) {
-  reset_frame_list_kernel<<<1, 64, 0, s>>>(m);
-  const int n = f.W * f.H;
-  const int grid = (n + 255) / 256;
-  if (depth_format == RF_DEPTH_U16)
-    alloc_kernel<RF_DEPTH_U16><<<grid, 256, 0, s>>>(m, f, pose, mask, frame_id);
-  else
-    alloc_kernel<RF_DEPTH_F32><<<grid, 256, 0, s>>>(m, f, pose, mask, frame_id);
+void launch_allocate(Batch& b, int depth_format, hipStream_t s) {
+  reset_frame_list_kernel<<<b.n, 64, 0, s>>>(b);
+  int total = 0;
+  for (int j = 0; j < b.n; ++j) {
+    Job& J = b.job[j];
+    const int n = J.f.W * J.f.H;
+    const int sc = (int)J.m.carve_stride;
+    J.band_groups = (n + 255) / 256;
+    J.carve_w = (J.f.W + sc - 1) / sc;
+    J.carve_h = (J.f.H + sc - 1) / sc;
+    b.base[j] = total;
+    total += J.band_groups + (J.carve_w * J.carve_h + 255) / 256;
+  }
+  b.base[b.n] = total;
+  if (depth_format == RF_DEPTH_U16) alloc_kernel<RF_DEPTH_U16><<<total, 256, 0, s>>>(b);
+  else alloc_kernel<RF_DEPTH_F32><<<total, 256, 0, s>>>(b);
 }
 
-int integrate_grid() { return 2048; }
-
-void launch_integrate(const MapDev& m, const FrameDev& f, int depth_format, int storage, const double* pose,
-                      const uint8_t* mask, hipStream_t s) {
-  const int grid = integrate_grid();
+void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
+  // a fixed share of workgroups per job (block counts live on the device)
+  const int per = b.n == 1 ? 8192 : (b.n <= 4 ? 4096 : 2048);
+  for (int j = 0; j <= b.n; ++j) b.base[j] = j * per;
+  const int grid = b.n * per;
   if (depth_format == RF_DEPTH_U16) {
-    if (storage == RF_STORAGE_FP32)
-      integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<grid, 256, 0, s>>>(m, f, pose, mask);
-    else
-      integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(m, f, pose, mask);
+    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<grid, 512, 0, s>>>(b);
+    else integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<grid, 512, 0, s>>>(b);
   } else {
-    if (storage == RF_STORAGE_FP32)
-      integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<grid, 256, 0, s>>>(m, f, pose, mask);
-    else
-      integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(m, f, pose, mask);
+    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<grid, 512, 0, s>>>(b);
+    else integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<grid, 512, 0, s>>>(b);
   }
 }
 

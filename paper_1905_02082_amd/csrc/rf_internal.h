@@ -1,4 +1,12 @@
-// Host-side declarations shared by the library's translation units.
+// Host-side declarations shared by the library's translation units, and the
+// job batch every per-frame kernel consumes.
+//
+// Every per-frame kernel works on a batch of up to kMaxBatch jobs passed by
+// value as a kernel argument (a job = one map + one frame + its pose, mask
+// and outputs).  The grid is the concatenation of the jobs' grids: base[j] is
+// the first workgroup of job j.  A single-map call is a batch of one, so the
+// multi-session path and the single-session path run the same kernels; a
+// job's result never depends on the other jobs in its batch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,6 +16,40 @@
 #include "rf_device.h"
 
 namespace rf {
+
+constexpr int kMaxBatch = 8;
+
+struct Job {
+  MapDev m;
+  FrameDev f;
+  const uint8_t* mask;      // input mask (nullable)
+  double* pose;             // device pose (in/out for tracking)
+  rf_track_stats* stats;    // nullable
+  uint8_t* mask_out;        // dynamic mask outputs
+  uint8_t* raw;
+  uint8_t* eroded;
+  uint8_t* filled;
+  float* residual;
+  uint32_t frame_id;        // allocation epoch
+  int tiles_x, tiles_y;     // flood-fill tile grid
+  int band_groups;          // allocation: workgroups of band rays
+  int carve_w, carve_h;     // allocation: carve-grid size
+};
+
+struct Batch {
+  int n;
+  int base[kMaxBatch + 1];
+  Job job[kMaxBatch];
+};
+
+static_assert(sizeof(Batch) <= 3072, "job batch must stay well inside the kernel-argument limit");
+
+// Job of workgroup g (uniform per workgroup).
+__device__ __forceinline__ int batch_job(const Batch& b, int g) {
+  int j = 0;
+  while (j + 1 < b.n && g >= b.base[j + 1]) ++j;
+  return j;
+}
 
 // Host view of one map: device pointers into the caller's arena plus the
 // parameters every launch needs.
@@ -19,19 +61,14 @@ struct HostMap {
   uint32_t frame_id;  // allocation epoch (frame stamps in the buckets)
 };
 
-void launch_allocate(const MapDev& m, const FrameDev& f, int depth_format, const double* pose,
-                     const uint8_t* mask, uint32_t frame_id, hipStream_t s);
-void launch_integrate(const MapDev& m, const FrameDev& f, int depth_format, int storage, const double* pose,
-                      const uint8_t* mask, hipStream_t s);
-void launch_track(const MapDev& m, const FrameDev& f, int depth_format, int storage,
-                  const rf_track_params& tp, const uint8_t* mask, double* pose, rf_track_stats* stats,
-                  hipStream_t s);
-void launch_normal_equations(const MapDev& m, const FrameDev& f, int depth_format, int storage,
-                             const uint8_t* mask, const double* pose, int level, float w_c, double* out29,
+// Launchers: b holds 1..kMaxBatch jobs sharing depth format and storage.
+void launch_allocate(Batch& b, int depth_format, hipStream_t s);
+void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s);
+void launch_track(Batch& b, int depth_format, int storage, const rf_track_params& tp, hipStream_t s);
+void launch_normal_equations(Batch& b, int depth_format, int storage, int level, float w_c, double* out29,
                              hipStream_t s);
-void launch_mask(const MapDev& m, const FrameDev& f, int depth_format, int storage, const double* pose,
-                 const rf_mask_params& mp, uint8_t* raw, uint8_t* eroded, uint8_t* filled, uint8_t* out,
-                 float* residual, hipStream_t s);
+void launch_mask(Batch& b, int depth_format, int storage, const rf_mask_params& mp, hipStream_t s);
+
 void launch_map_init(const MapDev& m, uint32_t num_buckets, int storage, hipStream_t s);
 void launch_surface(const MapDev& m, int storage, float* pts, uint32_t cap, uint32_t* count, hipStream_t s);
 void launch_frame_blocks(const MapDev& m, int32_t* keys, uint32_t cap, uint32_t* count, hipStream_t s);
@@ -39,6 +76,5 @@ void launch_export(const MapDev& m, int storage, int32_t* keys, float* sdf, floa
                    uint32_t cap, uint32_t* count, hipStream_t s);
 void launch_import(const MapDev& m, int storage, const int32_t* keys, const float* sdf, const float* w,
                    const uint8_t* rgb, uint32_t n, hipStream_t s);
-int integrate_grid();
 
 }  // namespace rf

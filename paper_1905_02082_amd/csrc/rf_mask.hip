@@ -1,7 +1,7 @@
 // Residual-based dynamics mask (Sec. III-C, Algorithm 1) for gfx950.
 //
 //   residual_kernel   r = S(T x)^2 per valid pixel, raw = r > gamma tau^2
-//   erode_kernel      3x3 erosion (outside the image counts as 0) -> seeds
+//   pixel_pass 0      3x3 erosion (outside the image counts as 0) -> seeds
 //   flood_tiles       every 32x32 tile (plus 1-pixel halo) in LDS grows the
 //                     seeds to its local fixpoint; a tile whose new border
 //                     pixels can reach an unset pixel of a neighbouring tile
@@ -10,7 +10,9 @@
 //                     no tile is dirty: growth is monotone, so the result is
 //                     the unique least fixpoint the queue of Algorithm 1
 //                     reaches, with no grid-wide barrier
-//   dilate_kernel     3x3 dilation -> final mask
+//   pixel_pass 1      3x3 dilation -> final mask
+// All passes take a batch of jobs (one map + frame each); the flood-fill
+// finish runs one workgroup per job.
 // The flood-fill rule: a neighbour n (8-neighbourhood) of a member p joins
 // when |D(p) - D(n)| < theta D(p); invalid pixels carry D = 0 and so never
 // join nor propagate.
@@ -20,18 +22,21 @@
 namespace rf {
 
 template <int DF, int STORAGE>
-__global__ __launch_bounds__(256) void residual_kernel(MapDev m, FrameDev f, const double* __restrict__ pose,
-                                                       float thr, uint8_t* __restrict__ raw,
-                                                       float* __restrict__ residual) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void residual_kernel(Batch b, float gamma) {
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  const FrameDev& f = J.f;
+  const int idx = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
   if (idx >= f.W * f.H) return;
   const int u = idx % f.W, v = idx / f.W;
   const float D = load_depth<DF>(f, idx);
+  const float thr = gamma * (m.tau * m.tau);
   uint8_t out = 0;
   float r = -1.0f;
   if (depth_ok(D, m.dmax)) {
     float R[9], t[3];
-    load_pose_f(pose, R, t);
+    load_pose_f(J.pose, R, t);
     const float x[3] = {(((float)u - f.cx) * f.ifx) * D, (((float)v - f.cy) * f.ify) * D, D};
     float y[3];
     xform(R, t, x, y);
@@ -41,14 +46,25 @@ __global__ __launch_bounds__(256) void residual_kernel(MapDev m, FrameDev f, con
       out = (r > thr) ? 1 : 0;
     }
   }
-  raw[idx] = out;
-  if (residual) residual[idx] = r;
+  (J.raw ? J.raw : J.mask_out)[idx] = out;
+  if (J.residual) J.residual[idx] = r;
 }
 
-__global__ __launch_bounds__(256) void morph_kernel(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, int W,
-                                                    int H, int erode) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// Per-pixel passes over the batch: 0 erode raw -> seeds, 1 dilate seeds ->
+// mask, 2 copy seeds to the caller's eroded output, 3 copy the fill.
+__global__ __launch_bounds__(256) void pixel_pass_kernel(Batch b, int pass) {
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const int W = J.f.W, H = J.f.H;
+  const int idx = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
   if (idx >= W * H) return;
+  if (pass >= 2) {
+    uint8_t* dst = (pass == 2) ? J.eroded : J.filled;
+    if (dst) dst[idx] = J.m.md[idx];
+    return;
+  }
+  const uint8_t* in = (pass == 0) ? (J.raw ? J.raw : J.mask_out) : J.m.md;
+  uint8_t* out = (pass == 0) ? J.m.md : J.mask_out;
   const int u = idx % W, v = idx / W;
   int all = 1, any = 0;
 #pragma unroll
@@ -60,7 +76,7 @@ __global__ __launch_bounds__(256) void morph_kernel(const uint8_t* __restrict__ 
       all &= val;
       any |= val;
     }
-  out[idx] = (uint8_t)(erode ? all : any);
+  out[idx] = (uint8_t)(pass == 0 ? all : any);
 }
 
 template <int DF>
@@ -151,12 +167,16 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
 }
 
 template <int DF>
-__global__ __launch_bounds__(256) void flood_tiles_kernel(MapDev m, FrameDev f, float theta, int tiles_x,
-                                                          int tiles_y) {
+__global__ __launch_bounds__(256) void flood_tiles_kernel(Batch b, float theta) {
   __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
   __shared__ float s_d[kHalo * kHalo];
   __shared__ int s_flag;
-  const int tx = blockIdx.x, ty = blockIdx.y;
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  const FrameDev& f = J.f;
+  const int g = blockIdx.x - b.base[jb];
+  const int tx = g % J.tiles_x, ty = g / J.tiles_x;
   // skip tiles whose halo holds no member at all
   const int u0 = tx * kTile - 1, v0 = ty * kTile - 1;
   int any = 0;
@@ -165,19 +185,24 @@ __global__ __launch_bounds__(256) void flood_tiles_kernel(MapDev m, FrameDev f, 
     if (u >= 0 && v >= 0 && u < f.W && v < f.H) any |= m.md[v * f.W + u];
   }
   if (!__syncthreads_or(any)) return;
-  flood_one_tile<DF>(m, f, theta, tx, ty, tiles_x, tiles_y, s_m, s_m0, s_d, &s_flag);
+  flood_one_tile<DF>(m, f, theta, tx, ty, J.tiles_x, J.tiles_y, s_m, s_m0, s_d, &s_flag);
 }
 
-// Single workgroup: process dirty tiles until none is left (or the work cap).
+// One workgroup per job: process dirty tiles until none is left (or the
+// work cap).
 template <int DF>
-__global__ __launch_bounds__(1024) void flood_finish_kernel(MapDev m, FrameDev f, float theta, int tiles_x,
-                                                            int tiles_y, int max_tiles_processed) {
+__global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta) {
   __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
   __shared__ float s_d[kHalo * kHalo];
   __shared__ int s_flag;
   __shared__ int s_list[1024];
   __shared__ int s_n;
+  const Job& J = b.job[blockIdx.x];
+  const MapDev& m = J.m;
+  const FrameDev& f = J.f;
+  const int tiles_x = J.tiles_x, tiles_y = J.tiles_y;
   const int ntiles = tiles_x * tiles_y;
+  const int max_tiles_processed = 64 * ntiles + f.W * f.H;
   int processed = 0;
   for (;;) {
     if (threadIdx.x == 0) s_n = 0;
@@ -206,44 +231,58 @@ __global__ __launch_bounds__(1024) void flood_finish_kernel(MapDev m, FrameDev f
   }
 }
 
-__global__ void clear_u32_kernel(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
+__global__ void clear_dirty_kernel(Batch b) {
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const int i = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
+  if (i < J.tiles_x * J.tiles_y) J.m.dirty[i] = 0;
 }
 
-__global__ void copy_u8_kernel(const uint8_t* __restrict__ a, uint8_t* __restrict__ b, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
+static int set_bases(Batch& b, int (*count)(const Job&)) {
+  int total = 0;
+  for (int j = 0; j < b.n; ++j) {
+    b.base[j] = total;
+    total += count(b.job[j]);
+  }
+  b.base[b.n] = total;
+  return total;
 }
+
+static int pixel_groups(const Job& J) { return (J.f.W * J.f.H + 255) / 256; }
+static int tile_count(const Job& J) { return J.tiles_x * J.tiles_y; }
+static int dirty_groups(const Job& J) { return (J.tiles_x * J.tiles_y + 255) / 256; }
 
 template <int DF, int STORAGE>
-static void mask_impl(const MapDev& m, const FrameDev& f, const double* pose, const rf_mask_params& mp,
-                      uint8_t* raw, uint8_t* eroded, uint8_t* filled, uint8_t* out, float* residual,
-                      hipStream_t s) {
-  const int n = f.W * f.H;
-  const int g = (n + 255) / 256;
-  const float tau = m.tau;
-  const float thr = mp.gamma * (tau * tau);
-  uint8_t* rawbuf = raw ? raw : out;
-  residual_kernel<DF, STORAGE><<<g, 256, 0, s>>>(m, f, pose, thr, rawbuf, residual);
-  morph_kernel<<<g, 256, 0, s>>>(rawbuf, m.md, f.W, f.H, 1);
-  if (eroded) copy_u8_kernel<<<g, 256, 0, s>>>(m.md, eroded, n);
-  const int tx = (f.W + kTile - 1) / kTile, ty = (f.H + kTile - 1) / kTile;
-  clear_u32_kernel<<<(tx * ty + 255) / 256, 256, 0, s>>>(m.dirty, tx * ty);
-  flood_tiles_kernel<DF><<<dim3(tx, ty), 256, 0, s>>>(m, f, mp.theta, tx, ty);
-  flood_finish_kernel<DF><<<1, 1024, 0, s>>>(m, f, mp.theta, tx, ty, 64 * tx * ty + n);
-  if (filled) copy_u8_kernel<<<g, 256, 0, s>>>(m.md, filled, n);
-  morph_kernel<<<g, 256, 0, s>>>(m.md, out, f.W, f.H, 0);
+static void mask_impl(Batch& b, const rf_mask_params& mp, hipStream_t s) {
+  bool eroded = false, filled = false;
+  for (int j = 0; j < b.n; ++j) {
+    Job& J = b.job[j];
+    J.tiles_x = (J.f.W + kTile - 1) / kTile;
+    J.tiles_y = (J.f.H + kTile - 1) / kTile;
+    eroded |= J.eroded != nullptr;
+    filled |= J.filled != nullptr;
+  }
+  int g = set_bases(b, pixel_groups);
+  residual_kernel<DF, STORAGE><<<g, 256, 0, s>>>(b, mp.gamma);
+  pixel_pass_kernel<<<g, 256, 0, s>>>(b, 0);
+  if (eroded) pixel_pass_kernel<<<g, 256, 0, s>>>(b, 2);
+  g = set_bases(b, dirty_groups);
+  clear_dirty_kernel<<<g, 256, 0, s>>>(b);
+  g = set_bases(b, tile_count);
+  flood_tiles_kernel<DF><<<g, 256, 0, s>>>(b, mp.theta);
+  flood_finish_kernel<DF><<<b.n, 1024, 0, s>>>(b, mp.theta);
+  g = set_bases(b, pixel_groups);
+  if (filled) pixel_pass_kernel<<<g, 256, 0, s>>>(b, 3);
+  pixel_pass_kernel<<<g, 256, 0, s>>>(b, 1);
 }
 
-void launch_mask(const MapDev& m, const FrameDev& f, int df, int st, const double* pose, const rf_mask_params& mp,
-                 uint8_t* raw, uint8_t* eroded, uint8_t* filled, uint8_t* out, float* residual, hipStream_t s) {
+void launch_mask(Batch& b, int df, int st, const rf_mask_params& mp, hipStream_t s) {
   if (df == RF_DEPTH_U16) {
-    if (st == RF_STORAGE_FP32) mask_impl<RF_DEPTH_U16, RF_STORAGE_FP32>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
-    else mask_impl<RF_DEPTH_U16, RF_STORAGE_FP16_U8>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
+    if (st == RF_STORAGE_FP32) mask_impl<RF_DEPTH_U16, RF_STORAGE_FP32>(b, mp, s);
+    else mask_impl<RF_DEPTH_U16, RF_STORAGE_FP16_U8>(b, mp, s);
   } else {
-    if (st == RF_STORAGE_FP32) mask_impl<RF_DEPTH_F32, RF_STORAGE_FP32>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
-    else mask_impl<RF_DEPTH_F32, RF_STORAGE_FP16_U8>(m, f, pose, mp, raw, eroded, filled, out, residual, s);
+    if (st == RF_STORAGE_FP32) mask_impl<RF_DEPTH_F32, RF_STORAGE_FP32>(b, mp, s);
+    else mask_impl<RF_DEPTH_F32, RF_STORAGE_FP16_U8>(b, mp, s);
   }
 }
 

@@ -242,14 +242,20 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
 }
 
 template <int DF, int STORAGE>
-__global__ __launch_bounds__(kTrackBlock) void track_kernel(MapDev m, FrameDev f, const uint8_t* __restrict__ mask,
-                                                            double* user_pose, TrackArgs a,
-                                                            rf_track_stats* __restrict__ stats) {
+__global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a) {
   __shared__ float s_t[kTerms][kTrackBlock + 1];
   __shared__ double s_g[kNE][kGroups + 1];
   __shared__ double s_ne[kNE];
   __shared__ double s_T[16];
   __shared__ int s_state;
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  const FrameDev& f = J.f;
+  const uint8_t* mask = J.mask;
+  double* user_pose = J.pose;
+  rf_track_stats* stats = J.stats;
+  const int g0 = blockIdx.x - b.base[jb];  // tile index within the job
   if (m.st->track_stop) return;  // uniform: set only by earlier launches
 
   // pose-independent loads first, so their latency overlaps the solve
@@ -259,8 +265,8 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(MapDev m, FrameDev f
   const int hl = (f.H + (1 << lv) - 1) >> lv;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tiles_x = (wl + kTileW - 1) / kTileW;
-  const int ul = (blockIdx.x % tiles_x) * kTileW + (wave % (kTileW / 8)) * 8 + (lane & 7);
-  const int vl = (blockIdx.x / tiles_x) * 16 + (wave / (kTileW / 8)) * 8 + (lane >> 3);
+  const int ul = (g0 % tiles_x) * kTileW + (wave % (kTileW / 8)) * 8 + (lane & 7);
+  const int vl = (g0 / tiles_x) * 16 + (wave / (kTileW / 8)) * 8 + (lane >> 3);
   bool live = false;
   int u = 0, v = 0, pix = 0;
   float D = 0.0f, Ipix = 0.0f;
@@ -275,18 +281,18 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(MapDev m, FrameDev f
       Ipix = luminance((float)px[0], (float)px[1], (float)px[2]);
     }
   }
-  if (blockIdx.x == 0 && a.acc_clear >= 0) {
+  if (g0 == 0 && a.acc_clear >= 0) {
     unsigned long long* c = acc_buf(m, a.acc_clear);
     for (int q = threadIdx.x; q < kBufWords; q += kTrackBlock) c[q] = 0ull;
   }
   if (threadIdx.x < 64) {
     if (a.solve) {
-      solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, blockIdx.x == 0);
+      solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, g0 == 0);
     } else {
       const double* Tin = pose_buf(m, user_pose, a.pose_read);
       if (threadIdx.x < 16) {
         s_T[threadIdx.x] = Tin[threadIdx.x];
-        if (blockIdx.x == 0) pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
+        if (g0 == 0) pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
       }
       if (threadIdx.x == 0) s_state = 0;
     }
@@ -368,16 +374,19 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(MapDev m, FrameDev f
     double tot = 0.0;
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) tot += s_g[threadIdx.x][g];
-    fixed_add(acc_buf(m, a.acc_write) + (blockIdx.x % kAccCopies) * kCopyWords + threadIdx.x * kTermWords, tot);
+    fixed_add(acc_buf(m, a.acc_write) + (g0 % kAccCopies) * kCopyWords + threadIdx.x * kTermWords, tot);
   }
 }
 
-// Solve of the last evaluation of a pass (or, in mode 1, the raw totals).
-__global__ __launch_bounds__(64) void track_finalize_kernel(MapDev m, double* user_pose, TrackArgs a,
-                                                            rf_track_stats* stats, double* out29) {
+// Solve of the last evaluation of a pass (or, in mode 1, the raw totals):
+// one workgroup per job.
+__global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a, double* out29) {
   __shared__ double s_ne[kNE];
   __shared__ double s_T[16];
   __shared__ int s_state;
+  const Job& J = b.job[blockIdx.x];
+  const MapDev& m = J.m;
+  double* user_pose = J.pose;
   if (a.mode == 1) {
     if (threadIdx.x < kNE) out29[threadIdx.x] = fixed_total(acc_buf(m, a.acc_read) + threadIdx.x * kTermWords);
     return;
@@ -387,15 +396,17 @@ __global__ __launch_bounds__(64) void track_finalize_kernel(MapDev m, double* us
     if (threadIdx.x < 16) user_pose[threadIdx.x] = pose_buf(m, user_pose, a.pose_read)[threadIdx.x];
     return;
   }
-  solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, true);
+  solve_step(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true);
 }
 
-__global__ void track_reset_kernel(MapDev m, rf_track_stats* stats) {
-  unsigned long long* acc = acc_buf(m, 0);
+__global__ void track_reset_kernel(Batch b) {
+  const Job& J = b.job[blockIdx.x];
+  unsigned long long* acc = acc_buf(J.m, 0);
   for (int q = threadIdx.x; q < 3 * kBufWords; q += blockDim.x) acc[q] = 0ull;
   if (threadIdx.x == 0) {
-    m.st->track_stop = 0;
-    m.st->track_counter = 0;
+    J.m.st->track_stop = 0;
+    J.m.st->track_counter = 0;
+    rf_track_stats* stats = J.stats;
     if (stats) {
       stats->cost = 0.0;
       stats->count = 0.0;
@@ -406,27 +417,30 @@ __global__ void track_reset_kernel(MapDev m, rf_track_stats* stats) {
   }
 }
 
-static int track_grid(const FrameDev& f, int level) {
+static int track_tiles(const FrameDev& f, int level) {
   const int wl = (f.W + (1 << level) - 1) >> level;
   const int hl = (f.H + (1 << level) - 1) >> level;
   return ((wl + kTileW - 1) / kTileW) * ((hl + 15) >> 4);
 }
 
-static void track_dispatch(const MapDev& m, const FrameDev& f, int df, int st, const uint8_t* mask, double* pose,
-                           const TrackArgs& a, rf_track_stats* stats, hipStream_t s) {
-  const int g = track_grid(f, a.level);
+static void track_dispatch(Batch& b, int df, int st, const TrackArgs& a, hipStream_t s) {
+  int total = 0;
+  for (int j = 0; j < b.n; ++j) {
+    b.base[j] = total;
+    total += track_tiles(b.job[j].f, a.level);
+  }
+  b.base[b.n] = total;
   if (df == RF_DEPTH_U16) {
-    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
-    else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
+    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<total, kTrackBlock, 0, s>>>(b, a);
+    else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<total, kTrackBlock, 0, s>>>(b, a);
   } else {
-    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
-    else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<g, kTrackBlock, 0, s>>>(m, f, mask, pose, a, stats);
+    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<total, kTrackBlock, 0, s>>>(b, a);
+    else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<total, kTrackBlock, 0, s>>>(b, a);
   }
 }
 
-void launch_track(const MapDev& m, const FrameDev& f, int df, int st, const rf_track_params& tp,
-                  const uint8_t* mask, double* pose, rf_track_stats* stats, hipStream_t s) {
-  track_reset_kernel<<<1, 256, 0, s>>>(m, stats);
+void launch_track(Batch& b, int df, int st, const rf_track_params& tp, hipStream_t s) {
+  track_reset_kernel<<<b.n, 256, 0, s>>>(b);
   int j = 0, prev_level = -1, prev_first = 0;
   for (int l = tp.levels - 1; l >= 0; --l)
     for (int it = 0; it < tp.iters_per_level; ++it, ++j) {
@@ -444,7 +458,7 @@ void launch_track(const MapDev& m, const FrameDev& f, int df, int st, const rf_t
       a.pose_read = j > 0 ? (j - 1) % 2 : 2;
       a.pose_write = j % 2;
       a.mode = 0;
-      track_dispatch(m, f, df, st, mask, pose, a, stats, s);
+      track_dispatch(b, df, st, a, s);
       prev_level = l;
       prev_first = it == 0;
     }
@@ -461,12 +475,12 @@ void launch_track(const MapDev& m, const FrameDev& f, int df, int st, const rf_t
   a.acc_clear = -1;
   a.pose_read = (j - 1) % 2;
   a.pose_write = 2;
-  track_finalize_kernel<<<1, 64, 0, s>>>(m, pose, a, stats, nullptr);
+  track_finalize_kernel<<<b.n, 64, 0, s>>>(b, a, nullptr);
 }
 
-void launch_normal_equations(const MapDev& m, const FrameDev& f, int df, int st, const uint8_t* mask,
-                             const double* pose, int level, float w_c, double* out29, hipStream_t s) {
-  track_reset_kernel<<<1, 256, 0, s>>>(m, nullptr);
+void launch_normal_equations(Batch& b, int df, int st, int level, float w_c, double* out29, hipStream_t s) {
+  for (int j = 0; j < b.n; ++j) b.job[j].stats = nullptr;
+  track_reset_kernel<<<b.n, 256, 0, s>>>(b);
   TrackArgs a{};
   a.level = level;
   a.w_c = w_c;
@@ -476,11 +490,11 @@ void launch_normal_equations(const MapDev& m, const FrameDev& f, int df, int st,
   a.acc_clear = -1;
   a.pose_read = 2;
   a.pose_write = 0;
-  track_dispatch(m, f, df, st, mask, const_cast<double*>(pose), a, nullptr, s);
-  TrackArgs b{};
-  b.mode = 1;
-  b.acc_read = 0;
-  track_finalize_kernel<<<1, 64, 0, s>>>(m, const_cast<double*>(pose), b, nullptr, out29);
+  track_dispatch(b, df, st, a, s);
+  TrackArgs c{};
+  c.mode = 1;
+  c.acc_read = 0;
+  track_finalize_kernel<<<b.n, 64, 0, s>>>(b, c, out29);
 }
 
 }  // namespace rf

@@ -47,6 +47,7 @@ int main(void) {
          sizeof(rf_mask_params), sizeof(rf_track_stats));
   printf("%zu %zu %zu %zu\\n", offsetof(rf_frame, depth), offsetof(rf_frame, rgb),
          offsetof(rf_track_params, lm_lambda), offsetof(rf_track_stats, level_count));
+  printf("%zu %zu %zu\\n", sizeof(rf_job), offsetof(rf_job, frame), offsetof(rf_job, d_stats));
   return 0;
 }
 ''')
@@ -54,7 +55,9 @@ int main(void) {
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     out = subprocess.check_output([str(exe)]).decode().split()
     sizes = [int(x) for x in out[:5]]
-    offs = [int(x) for x in out[5:]]
+    offs = [int(x) for x in out[5:9]]
+    job = [int(x) for x in out[9:]]
+    assert job == [ctypes.sizeof(N.RfJob), N.RfJob.frame.offset, N.RfJob.d_stats.offset]
     assert sizes == [ctypes.sizeof(N.RfFrame), ctypes.sizeof(N.RfMapParams), ctypes.sizeof(N.RfTrackParams),
                      ctypes.sizeof(N.RfMaskParams), ctypes.sizeof(N.RfTrackStats)]
     assert offs == [N.RfFrame.depth.offset, N.RfFrame.rgb.offset, N.RfTrackParams.lm_lambda.offset,
