@@ -68,7 +68,7 @@ Layout layout_of(const rf_map_params* p) {
   L.partials = o; o = align256(o + (size_t)rf::kTrackScratchWords * 8);
   L.md = o; o = align256(o + (size_t)p->max_pixels);
   L.dirty_cap = p->max_pixels / 16 + 64;
-  L.dirty = o; o = align256(o + (size_t)L.dirty_cap * 4);
+  L.dirty = o; o = align256(o + (size_t)L.dirty_cap * 2 * 4);  // two flag buffers
   L.total = o;
   return L;
 }

@@ -8,7 +8,7 @@
 //   sdfw         max_blocks x 512 x  {f32 sdf, f32 weight} (FP32) | {f16 sdf/tau, u8 weight, pad} (FP16)
 //   rgb          max_blocks x 512 x  uchar4 (RGB + pad)
 //   partials     tracking: 3 buffers of 29 fixed-point accumulators (128 B apart) + 2 poses
-//   mask scratch max_pixels bytes + per-tile dirty flags for the flood fill
+//   mask scratch max_pixels bytes + two buffers of per-tile dirty flags for the flood fill
 //
 // Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
 // linear probing, insertion by 64-bit CAS on the key word (insert-only: keys

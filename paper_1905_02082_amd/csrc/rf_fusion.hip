@@ -7,11 +7,11 @@
 // stamp, exchanged atomically), appended to the frame's block list.  Carve
 // rays run in workgroups of their own; cells are probed 8 at a time.
 //
-// Integration: one workgroup per listed block, one voxel per thread; a
-// voxel's record is written only when it is updated (occluded, masked and
-// out-of-view voxels are never stored).  Records are SoA per block, so a
-// workgroup's loads and stores are contiguous 4-KiB (FP32) / 2-KiB (FP16)
-// runs.
+// Integration: one workgroup per listed block, 256 threads x 2 voxels; a
+// voxel's record is read and written only when it is updated (occluded,
+// masked and out-of-view voxels cost no HBM traffic).  Records are SoA per
+// block, so a workgroup's loads and stores are contiguous 4-KiB (FP32) /
+// 2-KiB (FP16) runs.
 #include "rf_device.h"
 #include "rf_internal.h"
 
@@ -26,6 +26,24 @@ __device__ __forceinline__ void touch_block(const MapDev& m, int h, uint32_t sta
     const uint32_t i = atomicAdd(&m.st->f_count, 1u);
     if (i < m.flist_cap) m.flist[i] = (uint32_t)h;
   }
+}
+
+// True for exactly one active lane per distinct key among the lanes with
+// valid set (wavefront-level de-duplication: neighbouring rays visit the same
+// blocks, and only one of them needs to probe, insert or stamp a block).
+__device__ __forceinline__ bool wave_first_of_key(unsigned long long key, bool valid) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(valid);
+  bool leader = false;
+  while (todo) {
+    const int l = __ffsll((long long)todo) - 1;
+    const unsigned int klo = __builtin_amdgcn_readlane((unsigned int)key, l);
+    const unsigned int khi = __builtin_amdgcn_readlane((unsigned int)(key >> 32), l);
+    const unsigned long long k = ((unsigned long long)khi << 32) | klo;
+    todo &= ~__ballot(valid && key == k);
+    leader |= (lane == l);
+  }
+  return leader;
 }
 
 // Block-grid DDA of segment q0 -> q1 (block units): cells c = floor(q0) ...
@@ -142,8 +160,9 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
     Bucket bk[kBatch];
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
-      if (!ok[q]) continue;
       key[q] = pack_key(cx[q], cy[q], cz[q]);
+      ok[q] = wave_first_of_key(key[q], ok[q]);
+      if (!ok[q]) continue;
       hb[q] = hash3(cx[q], cy[q], cz[q]) & m.bucket_mask;
       bk[q] = m.buckets[hb[q]];
     }
@@ -170,65 +189,84 @@ __global__ void reset_frame_list_kernel(Batch b) {
 }
 
 // Integration of one frame into the blocks of the frame list: one
-// workgroup per listed block, one voxel per thread.  The voxel's sdf/weight
-// record is loaded before the keep/skip decision so that the load overlaps
-// the projection and the depth gather; it is stored only when updated.
+// workgroup per listed block at a time (grid-stride over the list), 256
+// threads x 2 voxels; both voxels of a thread are independent, so their
+// gathers overlap.  A voxel's record is read and written only when the frame
+// updates it.
+#ifndef RF_INTEG_SPEC
+#define RF_INTEG_SPEC 0
+#endif
+// Returns 0 (untouched), 1 (band update) or 2 (free-space update).
 template <int DF, int STORAGE>
-__global__ __launch_bounds__(512) void integrate_kernel(Batch b) {
+__device__ __forceinline__ int integrate_voxel(const MapDev& m, const FrameDev& f, const uint8_t* mask,
+                                               const float R[9], const float t[3], int bx, int by, int bz, int l,
+                                               uint32_t vidx) {
+#if RF_INTEG_SPEC
+  float sdf, W;
+  VoxelStore<STORAGE>::load(m, vidx, sdf, W);
+#endif
+  // X = R^T (v s - t), summed as (R0j d0 + R1j d1) + R2j d2
+  const float d0 = (float)(8 * bx + (l & 7)) * m.s - t[0];
+  const float d1 = (float)(8 * by + ((l >> 3) & 7)) * m.s - t[1];
+  const float d2 = (float)(8 * bz + (l >> 6)) * m.s - t[2];
+  const float X0 = (R[0] * d0 + R[3] * d1) + R[6] * d2;
+  const float X1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
+  const float X2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
+  if (!(X2 > 0.0f)) return 0;
+  const float uf = f.fx * (X0 / X2) + f.cx;
+  const float vf = f.fy * (X1 / X2) + f.cy;
+  const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
+  if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) return 0;
+  const int pix = (int)vr * f.W + (int)ur;
+  const float D = load_depth<DF>(f, pix);
+  if (!depth_ok(D, m.dmax)) return 0;
+  if (mask && mask[pix]) return 0;
+  const float eta = D - X2;
+  if (eta < -m.tau) return 0;
+  const bool band = (eta <= m.tau);
+  if (!band && !(X2 <= m.dmax)) return 0;
+  const float dval = band ? eta : m.tau;
+#if !RF_INTEG_SPEC
+  float sdf, W;
+  VoxelStore<STORAGE>::load(m, vidx, sdf, W);
+#endif
+  const float Wn = W + 1.0f;
+  VoxelStore<STORAGE>::store(m, vidx, (W * sdf + dval) / Wn, fminf(Wn, m.max_weight));
+  if (band) {
+    const uchar4 c = m.rgb[vidx];
+    const uint8_t* px = f.rgb + 3 * pix;
+    const float r = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.x + (float)px[0]) / Wn)));
+    const float g = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.y + (float)px[1]) / Wn)));
+    const float bl = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.z + (float)px[2]) / Wn)));
+    m.rgb[vidx] = make_uchar4((unsigned char)r, (unsigned char)g, (unsigned char)bl, 0);
+    return 1;
+  }
+  return 2;
+}
+
+template <int DF, int STORAGE>
+__global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const MapDev& m = J.m;
   const FrameDev& f = J.f;
   const uint8_t* mask = J.mask;
-  const double* pose = J.pose;
   const uint32_t g0 = blockIdx.x - b.base[jb], gn = b.base[jb + 1] - b.base[jb];
   const uint32_t nF = min(m.st->f_count, m.flist_cap);
   float R[9], t[3];
-  load_pose_f(pose, R, t);
+  load_pose_f(J.pose, R, t);
   uint32_t nb = 0, nf = 0;
-  const int l = threadIdx.x;
+  const int l0 = threadIdx.x, l1 = threadIdx.x + 256;
   for (uint32_t fi = g0; fi < nF; fi += gn) {
     const uint32_t h = m.flist[fi];
     const Bucket bu = m.buckets[h];
     if (bu.slot >= m.max_blocks) continue;
     int bx, by, bz;
     unpack_key(bu.key, bx, by, bz);
-    const uint32_t vidx = bu.slot * 512u + (uint32_t)l;
-    float sdf, W;
-    VoxelStore<STORAGE>::load(m, vidx, sdf, W);
-    const int vi[3] = {8 * bx + (l & 7), 8 * by + ((l >> 3) & 7), 8 * bz + (l >> 6)};
-    float d[3], X[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) d[a] = (float)vi[a] * m.s - t[a];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) X[j] = (R[j] * d[0] + R[3 + j] * d[1]) + R[6 + j] * d[2];
-    if (!(X[2] > 0.0f)) continue;
-    const float uf = f.fx * (X[0] / X[2]) + f.cx;
-    const float vf = f.fy * (X[1] / X[2]) + f.cy;
-    const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
-    if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) continue;
-    const int pix = (int)vr * f.W + (int)ur;
-    const float D = load_depth<DF>(f, pix);
-    if (!depth_ok(D, m.dmax)) continue;
-    if (mask && mask[pix]) continue;
-    const float eta = D - X[2];
-    if (eta < -m.tau) continue;
-    const bool band = (eta <= m.tau);
-    if (!band && !(X[2] <= m.dmax)) continue;
-    const float dval = band ? eta : m.tau;
-    const float Wn = W + 1.0f;
-    VoxelStore<STORAGE>::store(m, vidx, (W * sdf + dval) / Wn, fminf(Wn, m.max_weight));
-    if (band) {
-      const uchar4 c = m.rgb[vidx];
-      const uint8_t* px = f.rgb + 3 * pix;
-      const float r = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.x + (float)px[0]) / Wn)));
-      const float g = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.y + (float)px[1]) / Wn)));
-      const float bl = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.z + (float)px[2]) / Wn)));
-      m.rgb[vidx] = make_uchar4((unsigned char)r, (unsigned char)g, (unsigned char)bl, 0);
-      ++nb;
-    } else {
-      ++nf;
-    }
+    const int r0 = integrate_voxel<DF, STORAGE>(m, f, mask, R, t, bx, by, bz, l0, bu.slot * 512u + (uint32_t)l0);
+    const int r1 = integrate_voxel<DF, STORAGE>(m, f, mask, R, t, bx, by, bz, l1, bu.slot * 512u + (uint32_t)l1);
+    nb += (r0 == 1) + (r1 == 1);
+    nf += (r0 == 2) + (r1 == 2);
   }
   // per-workgroup update counts (band / free) for the roofline accounting
   __shared__ uint32_t s_cnt[2];
@@ -274,15 +312,15 @@ void launch_allocate(Batch& b, int depth_format, hipStream_t s) {
 
 void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
   // a fixed share of workgroups per job (block counts live on the device)
-  const int per = b.n == 1 ? 8192 : (b.n <= 4 ? 4096 : 2048);
+  const int per = b.n == 1 ? 2048 : (b.n <= 4 ? 1024 : 512);
   for (int j = 0; j <= b.n; ++j) b.base[j] = j * per;
   const int grid = b.n * per;
   if (depth_format == RF_DEPTH_U16) {
-    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<grid, 512, 0, s>>>(b);
-    else integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<grid, 512, 0, s>>>(b);
+    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<grid, 256, 0, s>>>(b);
+    else integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(b);
   } else {
-    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<grid, 512, 0, s>>>(b);
-    else integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<grid, 512, 0, s>>>(b);
+    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<grid, 256, 0, s>>>(b);
+    else integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(b);
   }
 }
 

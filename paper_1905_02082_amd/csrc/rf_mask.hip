@@ -5,7 +5,9 @@
 //   flood_tiles       every 32x32 tile (plus 1-pixel halo) in LDS grows the
 //                     seeds to its local fixpoint; a tile whose new border
 //                     pixels can reach an unset pixel of a neighbouring tile
-//                     marks that tile dirty
+//                     marks that tile dirty; a few more parallel passes
+//                     re-run only the dirty tiles (most marks made while
+//                     neighbours grew concurrently resolve here)
 //   flood_finish      one workgroup re-runs dirty tiles one at a time until
 //                     no tile is dirty: growth is monotone, so the result is
 //                     the unique least fixpoint the queue of Algorithm 1
@@ -87,13 +89,15 @@ __device__ __forceinline__ float flood_depth(const FrameDev& f, float dmax, int 
 }
 
 constexpr int kHalo = kTile + 2;
+constexpr int kFloodPasses = 5;  // parallel passes over dirty tiles before the one-workgroup drain
 
 // Grows the seeds of tile (tx,ty) to the tile-local fixpoint.  The halo is
 // read-only input.  Returns (in LDS) whether anything changed; marks the
 // neighbouring tiles that a newly set border pixel can reach.
 template <int DF>
 __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, int tx, int ty, int tiles_x,
-                               int tiles_y, uint8_t* s_m, uint8_t* s_m0, float* s_d, int* s_flag) {
+                               int tiles_y, uint8_t* s_m, uint8_t* s_m0, float* s_d, int* s_flag,
+                               uint32_t* mark) {
   const int nthr = blockDim.x;
   const int u0 = tx * kTile - 1, v0 = ty * kTile - 1;
   for (int i = threadIdx.x; i < kHalo * kHalo; i += nthr) {
@@ -106,6 +110,12 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
     s_d[i] = flood_depth<DF>(f, m.dmax, u, v);
   }
   __syncthreads();
+  // Local fixpoint.  A parallel pass over all pixels (every non-member checks
+  // its 8 neighbours) doubles as the convergence test; while it still finds
+  // new members, wavefront 0 runs four directional sweeps (left to right,
+  // right to left, top to bottom, bottom to top): lane t walks line t and
+  // each step checks the three neighbours on the side already swept, so one
+  // sweep carries a path that is monotone in its direction across the tile.
   for (;;) {
     if (threadIdx.x == 0) *s_flag = 0;
     __syncthreads();
@@ -138,6 +148,38 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
     const int again = *s_flag;
     __syncthreads();
     if (!again) break;
+    if (threadIdx.x < 64) {
+      const int t = threadIdx.x;
+#pragma unroll 1
+      for (int dir = 0; dir < 4; ++dir) {
+        const int back = (dir == 0) ? -1 : (dir == 1) ? 1 : (dir == 2) ? -kHalo : kHalo;
+        const int side = (dir < 2) ? kHalo : 1;
+#pragma unroll 1
+        for (int step = 0; step < kTile; ++step) {
+          if (t < kTile) {
+            const int i = (dir & 1) ? (kTile - 1 - step) : step;
+            const int c = (dir < 2) ? (1 + t) * kHalo + (1 + i) : (1 + i) * kHalo + (1 + t);
+            const float dq = s_d[c];
+            if (!s_m[c] && dq > 0.0f) {
+              bool join = false;
+#pragma unroll
+              for (int o = -1; o <= 1; ++o) {
+                const int n = c + back + o * side;
+                if (s_m[n]) {
+                  const float dp = s_d[n];
+                  join |= fabsf(dp - dq) < theta * dp;
+                }
+              }
+              if (join) s_m[c] = 1;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+    }
+    __syncthreads();
   }
   // write back new members; mark neighbours a new border member can reach
   for (int i = threadIdx.x; i < kTile * kTile; i += nthr) {
@@ -160,14 +202,18 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
         const int ntx = tx + (nlu < 0 ? -1 : (nlu >= kTile ? 1 : 0));
         const int nty = ty + (nlv < 0 ? -1 : (nlv >= kTile ? 1 : 0));
         if (ntx < 0 || nty < 0 || ntx >= tiles_x || nty >= tiles_y) continue;
-        m.dirty[nty * tiles_x + ntx] = 1;
+        mark[nty * tiles_x + ntx] = 1;
       }
   }
   __syncthreads();
 }
 
+// Parallel pass over the tiles of every job.  Pass 0 takes every tile with a
+// member in its halo and marks into dirty buffer 0; pass k > 0 takes the
+// tiles marked in buffer (k-1) % 2 (clearing their own flag) and marks into
+// buffer k % 2, so no pass reads the flags it writes.
 template <int DF>
-__global__ __launch_bounds__(256) void flood_tiles_kernel(Batch b, float theta) {
+__global__ __launch_bounds__(256) void flood_tiles_kernel(Batch b, float theta, int pass) {
   __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
   __shared__ float s_d[kHalo * kHalo];
   __shared__ int s_flag;
@@ -177,21 +223,29 @@ __global__ __launch_bounds__(256) void flood_tiles_kernel(Batch b, float theta) 
   const FrameDev& f = J.f;
   const int g = blockIdx.x - b.base[jb];
   const int tx = g % J.tiles_x, ty = g / J.tiles_x;
-  // skip tiles whose halo holds no member at all
-  const int u0 = tx * kTile - 1, v0 = ty * kTile - 1;
-  int any = 0;
-  for (int i = threadIdx.x; i < kHalo * kHalo; i += blockDim.x) {
-    const int u = u0 + i % kHalo, v = v0 + i / kHalo;
-    if (u >= 0 && v >= 0 && u < f.W && v < f.H) any |= m.md[v * f.W + u];
+  uint32_t* mark = m.dirty + (size_t)(pass & 1) * m.dirty_cap;
+  if (pass > 0) {
+    uint32_t* own = m.dirty + (size_t)((pass - 1) & 1) * m.dirty_cap + g;
+    if (!*own) return;  // uniform
+    __syncthreads();
+    if (threadIdx.x == 0) *own = 0;
+  } else {
+    // skip tiles whose halo holds no member at all
+    const int u0 = tx * kTile - 1, v0 = ty * kTile - 1;
+    int any = 0;
+    for (int i = threadIdx.x; i < kHalo * kHalo; i += blockDim.x) {
+      const int u = u0 + i % kHalo, v = v0 + i / kHalo;
+      if (u >= 0 && v >= 0 && u < f.W && v < f.H) any |= m.md[v * f.W + u];
+    }
+    if (!__syncthreads_or(any)) return;
   }
-  if (!__syncthreads_or(any)) return;
-  flood_one_tile<DF>(m, f, theta, tx, ty, J.tiles_x, J.tiles_y, s_m, s_m0, s_d, &s_flag);
+  flood_one_tile<DF>(m, f, theta, tx, ty, J.tiles_x, J.tiles_y, s_m, s_m0, s_d, &s_flag, mark);
 }
 
 // One workgroup per job: process dirty tiles until none is left (or the
 // work cap).
 template <int DF>
-__global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta) {
+__global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta, int buf) {
   __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
   __shared__ float s_d[kHalo * kHalo];
   __shared__ int s_flag;
@@ -203,16 +257,17 @@ __global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta
   const int tiles_x = J.tiles_x, tiles_y = J.tiles_y;
   const int ntiles = tiles_x * tiles_y;
   const int max_tiles_processed = 64 * ntiles + f.W * f.H;
+  uint32_t* dirty = m.dirty + (size_t)buf * m.dirty_cap;
   int processed = 0;
   for (;;) {
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
-      if (m.dirty[i]) {
-        m.dirty[i] = 0;
+      if (dirty[i]) {
+        dirty[i] = 0;
         const int k = atomicAdd(&s_n, 1);
         if (k < 1024) s_list[k] = i;
-        else m.dirty[i] = 1;  // no room this sweep: keep it for the next
+        else dirty[i] = 1;  // no room this sweep: keep it for the next
       }
     }
     __syncthreads();
@@ -221,7 +276,8 @@ __global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta
     if (n == 0) break;
     for (int k = 0; k < n; ++k) {
       const int tile = s_list[k];
-      flood_one_tile<DF>(m, f, theta, tile % tiles_x, tile / tiles_x, tiles_x, tiles_y, s_m, s_m0, s_d, &s_flag);
+      flood_one_tile<DF>(m, f, theta, tile % tiles_x, tile / tiles_x, tiles_x, tiles_y, s_m, s_m0, s_d, &s_flag,
+                         dirty);
     }
     processed += n;
     if (processed > max_tiles_processed) {
@@ -235,7 +291,10 @@ __global__ void clear_dirty_kernel(Batch b) {
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const int i = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
-  if (i < J.tiles_x * J.tiles_y) J.m.dirty[i] = 0;
+  if (i < J.tiles_x * J.tiles_y) {
+    J.m.dirty[i] = 0;
+    J.m.dirty[J.m.dirty_cap + i] = 0;
+  }
 }
 
 static int set_bases(Batch& b, int (*count)(const Job&)) {
@@ -269,8 +328,8 @@ static void mask_impl(Batch& b, const rf_mask_params& mp, hipStream_t s) {
   g = set_bases(b, dirty_groups);
   clear_dirty_kernel<<<g, 256, 0, s>>>(b);
   g = set_bases(b, tile_count);
-  flood_tiles_kernel<DF><<<g, 256, 0, s>>>(b, mp.theta);
-  flood_finish_kernel<DF><<<b.n, 1024, 0, s>>>(b, mp.theta);
+  for (int pass = 0; pass <= kFloodPasses; ++pass) flood_tiles_kernel<DF><<<g, 256, 0, s>>>(b, mp.theta, pass);
+  flood_finish_kernel<DF><<<b.n, 1024, 0, s>>>(b, mp.theta, kFloodPasses & 1);
   g = set_bases(b, pixel_groups);
   if (filled) pixel_pass_kernel<<<g, 256, 0, s>>>(b, 3);
   pixel_pass_kernel<<<g, 256, 0, s>>>(b, 1);

@@ -208,7 +208,7 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
 // publishes the pose, the statistics and, on a degenerate system, the stop
 // flag.  Returns through LDS: s_T (new pose), *s_state.
 __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& a, rf_track_stats* stats,
-                           double* s_ne, double* s_T, int* s_state, bool publish) {
+                           double* s_ne, double* s_T, int* s_state, bool publish, bool stopped) {
   const int lane = threadIdx.x;
   if (lane < kNE) s_ne[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -219,7 +219,7 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (!publish) return;
+  if (!publish || stopped) return;
   const int state = *s_state;
   if (lane < 16) {
     double* Tout = pose_buf(m, user_pose, a.pose_write);
@@ -256,7 +256,9 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   double* user_pose = J.pose;
   rf_track_stats* stats = J.stats;
   const int g0 = blockIdx.x - b.base[jb];  // tile index within the job
-  if (m.st->track_stop) return;  // uniform: set only by earlier launches
+  // Set only by earlier launches.  Read here but acted on after the pixel
+  // loads and the solve are under way: only publishing waits for it.
+  const uint32_t stopped = m.st->track_stop;
 
   // pose-independent loads first, so their latency overlaps the solve
   // workgroup = kTileW x 16 tile of the level's pixel grid, wavefront = 8x8 sub-tile
@@ -287,18 +289,18 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   }
   if (threadIdx.x < 64) {
     if (a.solve) {
-      solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, g0 == 0);
+      solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, g0 == 0, stopped != 0);
     } else {
       const double* Tin = pose_buf(m, user_pose, a.pose_read);
       if (threadIdx.x < 16) {
         s_T[threadIdx.x] = Tin[threadIdx.x];
-        if (g0 == 0) pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
+        if (g0 == 0 && !stopped) pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
       }
       if (threadIdx.x == 0) s_state = 0;
     }
   }
   __syncthreads();
-  if (s_state != 0) return;  // degenerate: pose kept, the pass stops
+  if (stopped || s_state != 0) return;  // stopped or degenerate: pose kept, the pass stops
 
   float term[kTerms];
 #pragma unroll
@@ -352,22 +354,19 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     } else if (k < 27) {
       r = k - 21;
     }
-    double acc = 0.0;
-    for (int p = g; p < kTrackBlock; p += kGroups) {
-      if (k < 21) {
-        acc = fma((double)s_t[r][p], (double)s_t[c][p], acc);
-        acc = fma(wc * (double)s_t[6 + r][p], (double)s_t[6 + c][p], acc);
-      } else if (k < 27) {
-        acc = fma((double)s_t[r][p], (double)s_t[12][p], acc);
-        acc = fma(wc * (double)s_t[6 + r][p], (double)s_t[13][p], acc);
-      } else if (k == 27) {
-        acc = fma((double)s_t[12][p], (double)s_t[12][p], acc);
-        acc = fma(wc * (double)s_t[13][p], (double)s_t[13][p], acc);
-      } else {
-        acc += (double)s_t[14][p];
+    // depth and photometric products in two independent chains
+    const int rd = (k < 21) ? r : (k < 27 ? r : 12), cd = (k < 21) ? c : 12;
+    const int rc = (k < 27) ? 6 + rd : 13, cc = (k < 21) ? 6 + c : 13;
+    double acc_d = 0.0, acc_c = 0.0;
+    if (k < 28) {
+      for (int p = g; p < kTrackBlock; p += kGroups) {
+        acc_d = fma((double)s_t[rd][p], (double)s_t[cd][p], acc_d);
+        acc_c = fma((double)s_t[rc][p], (double)s_t[cc][p], acc_c);
       }
+    } else {
+      for (int p = g; p < kTrackBlock; p += kGroups) acc_d += (double)s_t[14][p];
     }
-    s_g[k][g] = acc;
+    s_g[k][g] = acc_d + wc * acc_c;
   }
   __syncthreads();
   if (threadIdx.x < kNE) {
@@ -396,7 +395,7 @@ __global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a
     if (threadIdx.x < 16) user_pose[threadIdx.x] = pose_buf(m, user_pose, a.pose_read)[threadIdx.x];
     return;
   }
-  solve_step(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true);
+  solve_step(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true, false);
 }
 
 __global__ void track_reset_kernel(Batch b) {

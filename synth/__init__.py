@@ -268,13 +268,15 @@ def _orbit_trajectory(rng, n_frames, centre_z=1.4, radius=0.35, step_cm=(0.5, 2.
     return np.stack(poses)
 
 
-def _movers(rng, n_clusters, half):
+def _movers(rng, n_clusters, half, sweep):
     """Moving rigid clusters on circular floor paths around the room centre."""
     clusters = []
     for cid in range(1, n_clusters + 1):
         speed = rng.uniform(0.5, 1.5) / 30.0          # m per frame at 30 Hz
         radius = rng.uniform(0.95, 1.3)
         phase = rng.uniform(0, 2 * math.pi)
+        if sweep:                                     # start near the end of the swing: out of view
+            phase = 0.3 * (phase / (2 * math.pi) - 0.5)
         direction = 1 if rng.uniform() < 0.5 else -1
         parts = []
         if rng.uniform() < 0.6:
@@ -287,19 +289,27 @@ def _movers(rng, n_clusters, half):
             parts.append(box((0, 0, tall / 2), (rng.uniform(0.15, 0.35), rng.uniform(0.15, 0.35), tall / 2),
                              0.0, rng, cid))
             parts.append(box((0, 0, tall + 0.1), (0.12, 0.12, 0.1), 0.3, rng, cid))
-        clusters.append(dict(speed=speed, radius=radius, phase=phase, dir=direction, parts=parts))
+        clusters.append(dict(speed=speed, radius=radius, phase=phase, dir=direction, parts=parts, sweep=sweep))
     return clusters
 
 
 def _place_movers(clusters, k, cam_pose):
     """Cluster placement at frame k: each cluster walks back and forth across
-    the camera's heading on a circle about the room centre at its own speed."""
+    the camera's heading on a circle about the room centre at its own speed.
+    "sweep" clusters swing +-1.2 rad about the heading (the view is about
+    +-0.55 rad wide), so they enter and leave the view, and start outside it;
+    "in_view" clusters swing +-0.55 rad from a random phase, so short
+    sequences always see them."""
     f = cam_pose[:3, 2]
     yaw = math.atan2(f[1], f[0])
     out = []
     for c in clusters:
-        amp = 0.55
-        ang = yaw + c["dir"] * amp * math.sin(c["speed"] / (c["radius"] * amp) * k + c["phase"])
+        if c["sweep"]:
+            amp = 1.2
+            ang = yaw + c["dir"] * amp * math.cos(c["speed"] / (c["radius"] * amp) * k + c["phase"])
+        else:
+            amp = 0.55
+            ang = yaw + c["dir"] * amp * math.sin(c["speed"] / (c["radius"] * amp) * k + c["phase"])
         ox, oy = c["radius"] * math.cos(ang), c["radius"] * math.sin(ang)
         for p in c["parts"]:
             q = p.copy()
@@ -323,13 +333,19 @@ def static_room(n_frames=300, seed=1905020822, width=640, height=480):
                     levels=3, iters=10, carve_stride=4, seed=seed)
 
 
-def dynamic_room(n_frames=400, seed=1905020823, width=640, height=480, n_clusters=None):
+def dynamic_room(n_frames=400, seed=1905020823, width=640, height=480, n_clusters=None, movers="sweep"):
+    """Furnished room with 1-3 moving clusters (people-sized capsules or
+    boxes).  movers="sweep": clusters walk into and out of the view and are
+    outside it at frame 0 (the long-sequence workload); movers="in_view":
+    clusters stay near the view centre from frame 0 (short parity cases)."""
+    if movers not in ("sweep", "in_view"):
+        raise ValueError("movers must be 'sweep' or 'in_view'")
     rng = np.random.default_rng(seed)
     prims = _furnished_room(rng)
     fx = fy = 525.0 * width / 640.0
     cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
     poses = _orbit_trajectory(rng, n_frames)
-    clusters = _movers(rng, int(n_clusters or rng.integers(1, 4)), (2.0, 2.0, 1.5))
+    clusters = _movers(rng, int(n_clusters or rng.integers(1, 4)), (2.0, 2.0, 1.5), movers == "sweep")
     frames = [np.stack(prims + _place_movers(clusters, k, poses[k])) for k in range(n_frames)]
     depth, rgb, labels = render(np.stack(frames), poses, width, height, fx, fy, cx, cy,
                                 seed, noise=True, dropout=0.02)

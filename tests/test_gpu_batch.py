@@ -17,8 +17,8 @@ def rf():
 
 def sequences():
     return [synth.parity_room(n_frames=5),
-            synth.dynamic_room(n_frames=5, width=160, height=120, n_clusters=2),
-            synth.dynamic_room(n_frames=5, width=77, height=53, n_clusters=1, seed=7)]
+            synth.dynamic_room(n_frames=5, width=160, height=120, n_clusters=2, movers="in_view"),
+            synth.dynamic_room(n_frames=5, width=77, height=53, n_clusters=1, seed=7, movers="in_view")]
 
 
 def run(rf, seqs, batched, start_offsets=(0, 0, 0)):

@@ -34,7 +34,7 @@ def room():
 
 @pytest.fixture(scope="module")
 def dyn_small():
-    return synth.dynamic_room(n_frames=24, width=160, height=120, n_clusters=2)
+    return synth.dynamic_room(n_frames=24, width=160, height=120, n_clusters=2, movers="in_view")
 
 
 def integrate_teacher_forced(rf, seq, frames, storage="fp32", orc_storage=0, masks=None):
@@ -243,7 +243,7 @@ def test_empty_frame(rf, room):
 
 
 def test_ragged_image_sizes(rf):
-    seq = synth.dynamic_room(n_frames=8, width=77, height=53, n_clusters=1)
+    seq = synth.dynamic_room(n_frames=8, width=77, height=53, n_clusters=1, movers="in_view")
     masks = [None, None, None]
     m, o64, o32 = integrate_teacher_forced(rf, seq, range(0, 6, 2), masks=masks)
     assert_maps_match(m, o64, o32)

@@ -25,7 +25,7 @@ def rf():
 
 @pytest.fixture(scope="module")
 def setup(rf):
-    seq = synth.dynamic_room(n_frames=N_FUSE + 2, width=160, height=120, n_clusters=1)
+    seq = synth.dynamic_room(n_frames=N_FUSE + 2, width=160, height=120, n_clusters=1, movers="in_view")
     maps = {st: rf.Map(map_params(rf, seq, st, max_blocks=1 << 15)) for st in ("fp32", "fp16")}
     o64 = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=64)
     for k in range(N_FUSE):
