@@ -13,14 +13,16 @@ with carve rays, integration with free-space carving.  Frame 0 initialises
 the map; the first W frames are warmup; K frames are timed.  All inputs are
 on the device before the timed region.
 
-Prints ONE JSON line.  The dominant kernel's duration is measured with HIP
-events on the stream it runs on; its algorithmic bytes come from device
-counters of voxel updates (see the design doc for the per-unit figures).
+Prints ONE JSON line.  Kernel durations are measured with HIP events on the
+stream the kernels run on.  "roofline" is the dominant kernel (the tracking
+sweep): its algorithmic bytes come from the host footprint of sampled frames
+(distinct voxel records and buckets a sweep reads, plus image bytes).
+"roofline_integrate" is the integration kernel, whose algorithmic bytes come
+from device counters of voxel updates.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -37,25 +39,57 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("rf_fusion.hip", "rf_device.h"):
-        with open(os.path.join(ROOT, "paper_1905_02082_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def traffic_from_profile(workload, storage):
-    """HBM bytes per integration launch from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "integrate_%s_%s_pmc.json" % (workload, storage))
+def traffic_from_profile(kernel, workload, storage):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) per launch of `kernel`
+    from the committed rocprofv3 PMC summary, if it was taken on the current
+    kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_pmc.json" % (kernel.replace("_kernel", ""), workload, storage))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    from paper_1905_02082_amd.profiling import kernel_source_hash
+    if d.get("kernel_source_hash") != kernel_source_hash(kernel):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def track_footprint(seq, block_keys, frame_ids, storage):
+    """Algorithmic bytes of one tracking sweep (one track_kernel launch) per
+    pyramid level, averaged over frame_ids: every distinct voxel record a
+    trilinear lookup reads (corners inside allocated blocks), one hash bucket
+    per distinct corner block, the depth and colour of every pixel of the
+    level (and its mask byte in the masked pass), and the 29 FP64 sums
+    written.  Host arithmetic on the ground-truth pose of each frame."""
+    import numpy as np
+    rec = {"fp32": 12, "fp16": 8}[storage]
+    bkeys = np.asarray(block_keys, dtype=np.int64)
+    enc = lambda b: ((b[:, 0] + (1 << 20)) << 42) | ((b[:, 1] + (1 << 20)) << 21) | (b[:, 2] + (1 << 20))
+    have = np.sort(enc(bkeys)) if len(bkeys) else np.zeros(0, np.int64)
+    fx, fy, cx, cy = seq.intrinsics
+    corners = np.array([[i & 1, (i >> 1) & 1, i >> 2] for i in range(8)], dtype=np.int64)
+    out = np.zeros(seq.levels)
+    pix = np.zeros(seq.levels)
+    for k in frame_ids:
+        D = seq.depth[k].astype(np.float64) * (seq.depth_scale if seq.depth[k].dtype == np.uint16 else 1.0)
+        T = seq.poses[k]
+        for lv in range(seq.levels):
+            st = 1 << lv
+            d = D[::st, ::st]
+            v, u = np.mgrid[0:seq.height:st, 0:seq.width:st]
+            ok = (d > 0) & (d <= seq.depth_max)
+            x = np.stack([(u[ok] - cx) / fx * d[ok], (v[ok] - cy) / fy * d[ok], d[ok]], 1)
+            y = x @ T[:3, :3].T + T[:3, 3]
+            g = np.floor(y / seq.voxel_size).astype(np.int64)
+            vox = (g[:, None, :] + corners[None]).reshape(-1, 3)
+            blk = np.floor_divide(vox, 8)
+            bid = enc(blk)
+            ub = np.unique(bid)
+            alloc = np.isin(bid, have, assume_unique=False)
+            voxel_ids = np.unique(enc(vox[alloc] + (1 << 19)))  # any injective code of the voxel
+            out[lv] += voxel_ids.size * rec + ub.size * 16 + d.size * (2 + 3) + 29 * 8
+            pix[lv] += d.size
+    return out / max(len(frame_ids), 1), pix / max(len(frame_ids), 1)
 
 
 def make_sequence(workload, n):
@@ -253,6 +287,18 @@ def main():
     fps = K / wall
     T_final = pose.cpu().numpy()
 
+    # tracking roofline (the dominant kernel): algorithmic bytes per sweep from
+    # the host footprint of sampled frames; duration = tracking stage time /
+    # sweeps (each pass is levels x iterations track_kernel launches plus one
+    # reset and one finalize launch of a few microseconds, counted in)
+    keys = m.export()[0].cpu().numpy()
+    sample = list(range(W, n, max(1, K // 4)))[:4]
+    fp1, pix = track_footprint(seq, keys, sample, args.storage)
+    sweeps = seq.levels * seq.iters
+    track_alg = seq.iters * (2 * fp1.sum() + pix.sum()) / (2 * sweeps)
+    track_ms = float((per_stage[:, 0] + per_stage[:, 2]).mean()) / (2 * sweeps)
+    track_achieved = track_alg / (track_ms * 1e-3) / 1e9
+
     # integration roofline: algorithmic bytes per launch from the voxel-update counters
     band = c1[0] - c0[0]
     free = c1[1] - c0[1]
@@ -264,7 +310,8 @@ def main():
     alg_per_launch = alg_bytes / max(launches, 1)
     integ_ms = float(per_stage[:, 4].mean())
     achieved = alg_per_launch / (integ_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(args.workload, args.storage)
+    traffic = traffic_from_profile("integrate_kernel", args.workload, args.storage)
+    track_traffic = traffic_from_profile("track_kernel", args.workload, args.storage)
 
     # trajectory error against the generator's ground truth (context only)
     E = np.linalg.inv(seq.poses[n - 1]) @ T_final
@@ -291,7 +338,14 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(frame_ms, 50)), 4),
                        "p99": round(float(np.percentile(frame_ms, 99)), 4)},
         "stages_ms": {nm: round(float(per_stage[:, j].mean()), 4) for j, nm in enumerate(stage_names)},
-        "roofline": {"kernel": "integrate_kernel", "bound": "hbm", "achieved": round(achieved, 2),
+        "roofline": {"kernel": "track_kernel", "bound": "hbm", "achieved": round(track_achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(track_achieved / HBM_PEAK_GBS, 4),
+                     "traffic": track_traffic,
+                     "alg_bytes_per_launch": int(track_alg),
+                     "avg_launch_ms": round(track_ms, 5),
+                     "launches_per_step": 2 * sweeps,
+                     "alg_bytes_per_level": [int(x) for x in fp1]},
+        "roofline_integrate": {"kernel": "integrate_kernel", "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "alg_bytes_per_launch": int(alg_per_launch),

@@ -279,16 +279,17 @@ __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], fl
   // Corner k = dx + 2 dy + 4 dz lies in block (b0 + d) & cross; the distinct
   // blocks are the corners k with k & ~cross == 0.  Their first probes are
   // issued together (one round trip), and only collisions probe further.
-  unsigned long long key[8];
-  uint32_t hb[8];
-  Bucket bk[8];
+  // Only the loaded key and slot stay live across the round trip; the key
+  // and home bucket are recomputed afterwards (cheaper than registers).
+  unsigned long long bkey[8];
+  uint32_t bslot[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if ((k & ~cross) != 0) continue;
     const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
-    key[k] = pack_key(x, y, z);
-    hb[k] = hash3(x, y, z) & m.bucket_mask;
-    bk[k] = m.buckets[hb[k]];
+    const Bucket* p = m.buckets + (hash3(x, y, z) & m.bucket_mask);
+    bkey[k] = p->key;
+    bslot[k] = p->slot;
   }
   int sl[8];
 #pragma unroll
@@ -297,22 +298,41 @@ __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], fl
       sl[k] = sl[k & cross];
       continue;
     }
-    sl[k] = resolve_slot(m, bk[k], key[k], hb[k]);
+    const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
+    Bucket b0;
+    b0.key = bkey[k];
+    b0.slot = bslot[k];
+    sl[k] = resolve_slot(m, b0, pack_key(x, y, z), hash3(x, y, z) & m.bucket_mask);
     if (sl[k] < 0) return false;
   }
-  float cs[8], ci[8];
+  // All corner records (and colours) are loaded before any weight is
+  // tested, so the loads share one round trip instead of one each.  The
+  // empty asm statements pin every loaded value to this point: without them
+  // the compiler sinks each load into the branch that first uses it, which
+  // turns the gathers back into a chain of round trips.
+  float cs[8], cw[8], ci[8];
+  uint32_t cc[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
     const uint32_t idx = (uint32_t)sl[k] * 512u + (uint32_t)(((i0[0] + dx) & 7) + 8 * ((i0[1] + dy) & 7) +
                                                              64 * ((i0[2] + dz) & 7));
-    float w;
-    VoxelStore<STORAGE>::load(m, idx, cs[k], w);
-    if (!(w > 0.0f)) return false;
-    if (WANT_COLOUR) {
-      const uchar4 c = m.rgb[idx];
-      ci[k] = luminance((float)c.x, (float)c.y, (float)c.z);
-    }
+    VoxelStore<STORAGE>::load(m, idx, cs[k], cw[k]);
+    if (WANT_COLOUR) cc[k] = reinterpret_cast<const uint32_t*>(m.rgb)[idx];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    asm volatile("" : "+v"(cs[k]), "+v"(cw[k]));
+    if (WANT_COLOUR) asm volatile("" : "+v"(cc[k]));
+  }
+  bool observed = true;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) observed &= cw[k] > 0.0f;
+  if (!observed) return false;
+  if (WANT_COLOUR) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      ci[k] = luminance((float)(cc[k] & 0xFFu), (float)((cc[k] >> 8) & 0xFFu), (float)((cc[k] >> 16) & 0xFFu));
   }
   float dg[3];
   trilinear(cs, fr, S, dg, WANT_GRAD);

@@ -5,28 +5,17 @@
 // carve) segment with a DDA; each visited block is inserted into the hash by
 // CAS and, the first time it is touched in this frame (per-bucket frame
 // stamp, exchanged atomically), appended to the frame's block list.  Carve
-// rays run in workgroups of their own; cells are probed 8 at a time.
+// rays run in workgroups of their own; cells are probed 8 at a time, with
+// their bucket loads, stamp exchanges and list appends each issued together.
 //
-// Integration: one workgroup per listed block, 256 threads x 2 voxels; a
-// voxel's record is read and written only when it is updated (occluded,
-// masked and out-of-view voxels cost no HBM traffic).  Records are SoA per
-// block, so a workgroup's loads and stores are contiguous 4-KiB (FP32) /
-// 2-KiB (FP16) runs.
+// Integration: workgroups stride over the listed blocks, 256 threads x 2
+// voxels per block, two blocks per step; only voxels the frame updates are
+// written.  Records are SoA per block, so a workgroup's loads and stores are
+// contiguous 4-KiB (FP32) / 2-KiB (FP16) runs.
 #include "rf_device.h"
 #include "rf_internal.h"
 
 namespace rf {
-
-// Records a block of the frame: first touch this frame (stamp exchanged
-// atomically) appends its bucket to the frame list.  stamp0 is the stamp
-// value seen by the probe: equal to frame_id means already recorded.
-__device__ __forceinline__ void touch_block(const MapDev& m, int h, uint32_t stamp0, uint32_t frame_id) {
-  if (stamp0 == frame_id) return;
-  if (atomicExch(&m.buckets[h].stamp, frame_id) != frame_id) {
-    const uint32_t i = atomicAdd(&m.st->f_count, 1u);
-    if (i < m.flist_cap) m.flist[i] = (uint32_t)h;
-  }
-}
 
 // True for exactly one active lane per distinct key among the lanes with
 // valid set (wavefront-level de-duplication: neighbouring rays visit the same
@@ -166,14 +155,47 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
       hb[q] = hash3(cx[q], cy[q], cz[q]) & m.bucket_mask;
       bk[q] = m.buckets[hb[q]];
     }
+    // Stamp every cell's bucket with the frame (exchanges issued together);
+    // the cells whose old stamp differed are this frame's first touches.
+    uint32_t old[kBatch];
+    int hq[kBatch];
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
+      old[q] = frame_id;
+      hq[q] = -1;
       if (!ok[q]) continue;
       if (bk[q].key == key[q]) {
-        touch_block(m, (int)hb[q], bk[q].stamp, frame_id);
+        hq[q] = (int)hb[q];
+        if (bk[q].stamp != frame_id) old[q] = atomicExch(&m.buckets[hb[q]].stamp, frame_id);
       } else {
-        const int h = insert_block(m, cx[q], cy[q], cz[q]);
-        if (h >= 0) touch_block(m, h, m.buckets[h].stamp, frame_id);
+        hq[q] = insert_block(m, cx[q], cy[q], cz[q]);
+        if (hq[q] >= 0) old[q] = atomicExch(&m.buckets[hq[q]].stamp, frame_id);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) asm volatile("" : "+v"(old[q]));
+    // First touches are appended to the frame list with one counter atomic
+    // per wavefront and batch (ballot + mbcnt give each its position).
+    const int lane = threadIdx.x & 63;
+    uint32_t tot = 0, off[kBatch];
+    bool first[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      first[q] = hq[q] >= 0 && old[q] != frame_id;
+      const unsigned long long bq = __ballot(first[q]);
+      off[q] = tot + __builtin_amdgcn_mbcnt_hi((uint32_t)(bq >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bq, 0u));
+      tot += (uint32_t)__popcll(bq);
+    }
+    if (tot) {
+      const int leader = __ffsll((long long)__ballot(true)) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&m.st->f_count, tot);
+      base = __builtin_amdgcn_readlane(base, leader);
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        if (!first[q]) continue;
+        const uint32_t i = base + off[q];
+        if (i < m.flist_cap) m.flist[i] = (uint32_t)hq[q];
       }
     }
   }
@@ -188,85 +210,121 @@ __global__ void reset_frame_list_kernel(Batch b) {
   }
 }
 
-// Integration of one frame into the blocks of the frame list: one
-// workgroup per listed block at a time (grid-stride over the list), 256
-// threads x 2 voxels; both voxels of a thread are independent, so their
-// gathers overlap.  A voxel's record is read and written only when the frame
-// updates it.
-#ifndef RF_INTEG_SPEC
-#define RF_INTEG_SPEC 0
-#endif
-// Returns 0 (untouched), 1 (band update) or 2 (free-space update).
-template <int DF, int STORAGE>
-__device__ __forceinline__ int integrate_voxel(const MapDev& m, const FrameDev& f, const uint8_t* mask,
-                                               const float R[9], const float t[3], int bx, int by, int bz, int l,
-                                               uint32_t vidx) {
-#if RF_INTEG_SPEC
-  float sdf, W;
-  VoxelStore<STORAGE>::load(m, vidx, sdf, W);
-#endif
-  // X = R^T (v s - t), summed as (R0j d0 + R1j d1) + R2j d2
-  const float d0 = (float)(8 * bx + (l & 7)) * m.s - t[0];
-  const float d1 = (float)(8 * by + ((l >> 3) & 7)) * m.s - t[1];
-  const float d2 = (float)(8 * bz + (l >> 6)) * m.s - t[2];
-  const float X0 = (R[0] * d0 + R[3] * d1) + R[6] * d2;
-  const float X1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
-  const float X2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
-  if (!(X2 > 0.0f)) return 0;
-  const float uf = f.fx * (X0 / X2) + f.cx;
-  const float vf = f.fy * (X1 / X2) + f.cy;
-  const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
-  if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) return 0;
-  const int pix = (int)vr * f.W + (int)ur;
-  const float D = load_depth<DF>(f, pix);
-  if (!depth_ok(D, m.dmax)) return 0;
-  if (mask && mask[pix]) return 0;
-  const float eta = D - X2;
-  if (eta < -m.tau) return 0;
-  const bool band = (eta <= m.tau);
-  if (!band && !(X2 <= m.dmax)) return 0;
-  const float dval = band ? eta : m.tau;
-#if !RF_INTEG_SPEC
-  float sdf, W;
-  VoxelStore<STORAGE>::load(m, vidx, sdf, W);
-#endif
-  const float Wn = W + 1.0f;
-  VoxelStore<STORAGE>::store(m, vidx, (W * sdf + dval) / Wn, fminf(Wn, m.max_weight));
-  if (band) {
-    const uchar4 c = m.rgb[vidx];
-    const uint8_t* px = f.rgb + 3 * pix;
-    const float r = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.x + (float)px[0]) / Wn)));
-    const float g = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.y + (float)px[1]) / Wn)));
-    const float bl = fminf(255.0f, fmaxf(0.0f, rintf((W * (float)c.z + (float)px[2]) / Wn)));
-    m.rgb[vidx] = make_uchar4((unsigned char)r, (unsigned char)g, (unsigned char)bl, 0);
-    return 1;
-  }
-  return 2;
-}
+// Integration of one frame into the blocks of the frame list (Sec. III-A
+// running average, Sec. III-D carving).  Workgroups stride over the list and
+// take kIntegBlocks listed blocks per step; a thread owns voxels l and l + 256
+// of each.  Every load a step needs is issued before any result is used: the
+// list entries and buckets (uniform, one round trip each for all the step's
+// blocks), then the depth, the mask byte and the voxel record of every voxel
+// together.  The record is read even for voxels the frame leaves untouched
+// (about a fifth of a listed block), which costs those bytes but saves a
+// dependent round trip; only voxels the frame updates are written.
+constexpr int kIntegBlocks = 2;
 
 template <int DF, int STORAGE>
 __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
+  constexpr int NV = 2 * kIntegBlocks;  // voxels per thread per step
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
-  const MapDev& m = J.m;
-  const FrameDev& f = J.f;
+  // copies: the fields are read once, not at every use inside the branches
+  const MapDev m = J.m;
+  const FrameDev f = J.f;
   const uint8_t* mask = J.mask;
+  const uint8_t* mask_src = mask ? mask : f.rgb;  // a readable plane when there is no mask
   const uint32_t g0 = blockIdx.x - b.base[jb], gn = b.base[jb + 1] - b.base[jb];
   const uint32_t nF = min(m.st->f_count, m.flist_cap);
   float R[9], t[3];
   load_pose_f(J.pose, R, t);
   uint32_t nb = 0, nf = 0;
-  const int l0 = threadIdx.x, l1 = threadIdx.x + 256;
-  for (uint32_t fi = g0; fi < nF; fi += gn) {
-    const uint32_t h = m.flist[fi];
-    const Bucket bu = m.buckets[h];
-    if (bu.slot >= m.max_blocks) continue;
-    int bx, by, bz;
-    unpack_key(bu.key, bx, by, bz);
-    const int r0 = integrate_voxel<DF, STORAGE>(m, f, mask, R, t, bx, by, bz, l0, bu.slot * 512u + (uint32_t)l0);
-    const int r1 = integrate_voxel<DF, STORAGE>(m, f, mask, R, t, bx, by, bz, l1, bu.slot * 512u + (uint32_t)l1);
-    nb += (r0 == 1) + (r1 == 1);
-    nf += (r0 == 2) + (r1 == 2);
+  for (uint32_t f0 = g0; f0 < nF; f0 += kIntegBlocks * gn) {
+    uint32_t hb[kIntegBlocks];
+#pragma unroll
+    for (int i = 0; i < kIntegBlocks; ++i) {
+      const uint32_t fi = f0 + i * gn;
+      hb[i] = m.flist[fi < nF ? fi : f0];
+    }
+    Bucket bu[kIntegBlocks];
+#pragma unroll
+    for (int i = 0; i < kIntegBlocks; ++i) bu[i] = m.buckets[hb[i]];
+    int pix[NV];
+    uint32_t vidx[NV];
+    float X2[NV];
+    bool vis[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int i = v >> 1;
+      const int l = threadIdx.x + 256 * (v & 1);
+      const bool ok = f0 + i * gn < nF && bu[i].slot < m.max_blocks;
+      int bx, by, bz;
+      unpack_key(bu[i].key, bx, by, bz);
+      vidx[v] = ok ? bu[i].slot * 512u + (uint32_t)l : 0u;
+      // X = R^T (v s - t), summed as (R0j d0 + R1j d1) + R2j d2
+      const float d0 = (float)(8 * bx + (l & 7)) * m.s - t[0];
+      const float d1 = (float)(8 * by + ((l >> 3) & 7)) * m.s - t[1];
+      const float d2 = (float)(8 * bz + (l >> 6)) * m.s - t[2];
+      const float x0 = (R[0] * d0 + R[3] * d1) + R[6] * d2;
+      const float x1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
+      const float x2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
+      bool in = ok && x2 > 0.0f;
+      const float uf = f.fx * (x0 / x2) + f.cx;
+      const float vf = f.fy * (x1 / x2) + f.cy;
+      const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
+      in = in && ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H;
+      pix[v] = in ? (int)vr * f.W + (int)ur : 0;
+      X2[v] = x2;
+      vis[v] = in;
+    }
+    float D[NV], sdf[NV], W[NV];
+    uint32_t mk[NV], cpx[NV][3];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      D[v] = load_depth<DF>(f, pix[v]);
+      mk[v] = mask_src[pix[v]];
+      VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
+      const uint8_t* px = f.rgb + 3 * pix[v];  // the frame's colour (used by band voxels)
+      cpx[v][0] = px[0];
+      cpx[v][1] = px[1];
+      cpx[v][2] = px[2];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      asm volatile("" : "+v"(D[v]), "+v"(mk[v]), "+v"(sdf[v]), "+v"(W[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]),
+                   "+v"(cpx[v][2]));
+    // sdf and weight of every updated voxel; the band voxels then update
+    // their colour, with all colour loads of the step issued together
+    bool band[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      band[v] = false;
+      if (!vis[v] || !depth_ok(D[v], m.dmax) || (mask && mk[v])) continue;
+      const float eta = D[v] - X2[v];
+      if (eta < -m.tau) continue;
+      band[v] = (eta <= m.tau);
+      if (!band[v] && !(X2[v] <= m.dmax)) continue;
+      const float dval = band[v] ? eta : m.tau;
+      VoxelStore<STORAGE>::store(m, vidx[v], (W[v] * sdf[v] + dval) / (W[v] + 1.0f),
+                                 fminf(W[v] + 1.0f, m.max_weight));
+      nb += band[v];
+      nf += !band[v];
+    }
+    uint32_t cold[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      cold[v] = 0u;
+      if (band[v]) cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (!band[v]) continue;
+      const float Wv = W[v], Wn = W[v] + 1.0f;
+      float ch[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        ch[q] = fminf(255.0f, fmaxf(0.0f, rintf((Wv * (float)((cold[v] >> (8 * q)) & 0xFFu) + (float)cpx[v][q]) / Wn)));
+      m.rgb[vidx[v]] = make_uchar4((unsigned char)ch[0], (unsigned char)ch[1], (unsigned char)ch[2], 0);
+    }
   }
   // per-workgroup update counts (band / free) for the roofline accounting
   __shared__ uint32_t s_cnt[2];
@@ -311,8 +369,9 @@ void launch_allocate(Batch& b, int depth_format, hipStream_t s) {
 }
 
 void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
-  // a fixed share of workgroups per job (block counts live on the device)
-  const int per = b.n == 1 ? 2048 : (b.n <= 4 ? 1024 : 512);
+  // a fixed share of workgroups per job (block counts live on the device):
+  // together one resident round (6 workgroups of 256 threads per CU)
+  const int per = 1536 / b.n;
   for (int j = 0; j <= b.n; ++j) b.base[j] = j * per;
   const int grid = b.n * per;
   if (depth_format == RF_DEPTH_U16) {

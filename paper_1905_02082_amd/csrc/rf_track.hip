@@ -51,6 +51,13 @@ struct TrackArgs {
 __device__ __forceinline__ unsigned long long* acc_buf(const MapDev& m, int b) {
   return reinterpret_cast<unsigned long long*>(m.partials) + (size_t)b * kBufWords;
 }
+// The words an accumulator buffer actually uses: three chunks per term per
+// copy (the rest of each 128-byte line is padding against false sharing).
+constexpr int kUsedWords = kAccCopies * kNE * 3;
+__device__ __forceinline__ unsigned long long* used_word(unsigned long long* buf, int q) {
+  const int copy = q / (kNE * 3), r = q % (kNE * 3);
+  return buf + copy * kCopyWords + (r / 3) * kTermWords + (r % 3);
+}
 __device__ __forceinline__ double* pose_buf(const MapDev& m, double* user, int b) {
   return b == 2 ? user : reinterpret_cast<double*>(m.partials) + (size_t)3 * kBufWords + 16 * b;
 }
@@ -112,7 +119,9 @@ __device__ __forceinline__ int tri_index(int i, int j) {  // H(i,j), i <= j, pac
 // 0 ok, RF_FLAG_TRACK_FEW_PIXELS or RF_FLAG_TRACK_SINGULAR (pose kept).
 // A pivot of the elimination equals the squared Cholesky pivot, so the
 // singularity test is the Cholesky one: pivot <= 1e-12 trace(H).
-__device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const double* Tin, double* s_T,
+// tin[0..2] = Tin[ec], Tin[4 + ec], Tin[8 + ec] and tin[3] = Tin[lane] for
+// lanes < 16 (element (er, ec) = (lane / 4, lane % 4) of the input pose).
+__device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const double tin[4], double* s_T,
                                   int* s_state) {
   const int lane = threadIdx.x;
   int state = 0;
@@ -156,7 +165,7 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
     if (lane >= 12) {
       out = (lane == 15) ? 1.0 : 0.0;
     } else if (state != 0) {
-      out = Tin[lane];
+      out = tin[3];
     } else {
       // exp of the twist (rho, phi) = x: R = I + A K + B K^2, t = (I + B K + C K^2) rho
       const double p0 = x[3], p1 = x[4], p2 = x[5];
@@ -195,7 +204,7 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
         const double ccr[3] = {p1 * cr[2] - p2 * cr[1], p2 * cr[0] - p0 * cr[2], p0 * cr[1] - p1 * cr[0]};
         E[3] = rho[er] + B * cr[er] + C * ccr[er];
       }
-      out = E[0] * Tin[ec] + E[1] * Tin[4 + ec] + E[2] * Tin[8 + ec];
+      out = E[0] * tin[0] + E[1] * tin[1] + E[2] * tin[2];
       if (ec == 3) out += E[3];
     }
     s_T[lane] = out;
@@ -210,12 +219,21 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
 __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& a, rf_track_stats* stats,
                            double* s_ne, double* s_T, int* s_state, bool publish, bool stopped) {
   const int lane = threadIdx.x;
+  // the input pose is fetched together with the totals (one round trip)
+  double tin[4] = {0.0, 0.0, 0.0, 0.0};
+  if (lane < 16) {
+    const double* Tin = pose_buf(m, user_pose, a.pose_read);
+    const int ec = lane & 3;
+    tin[0] = Tin[ec];
+    tin[1] = Tin[4 + ec];
+    tin[2] = Tin[8 + ec];
+    tin[3] = Tin[lane];
+  }
   if (lane < kNE) s_ne[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const double* Tin = pose_buf(m, user_pose, a.pose_read);
-  solve_update_wave(s_ne, a, Tin, s_T, s_state);
+  solve_update_wave(s_ne, a, tin, s_T, s_state);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -269,23 +287,22 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   const int tiles_x = (wl + kTileW - 1) / kTileW;
   const int ul = (g0 % tiles_x) * kTileW + (wave % (kTileW / 8)) * 8 + (lane & 7);
   const int vl = (g0 / tiles_x) * 16 + (wave / (kTileW / 8)) * 8 + (lane >> 3);
-  bool live = false;
-  int u = 0, v = 0, pix = 0;
-  float D = 0.0f, Ipix = 0.0f;
-  if (ul < wl && vl < hl) {
-    u = ul << lv;
-    v = vl << lv;
-    pix = v * f.W + u;
-    D = load_depth<DF>(f, pix);
-    live = depth_ok(D, m.dmax) && !(mask && mask[pix]);
-    if (live) {
-      const uint8_t* px = f.rgb + 3 * pix;
-      Ipix = luminance((float)px[0], (float)px[1], (float)px[2]);
-    }
-  }
-  if (g0 == 0 && a.acc_clear >= 0) {
-    unsigned long long* c = acc_buf(m, a.acc_clear);
-    for (int q = threadIdx.x; q < kBufWords; q += kTrackBlock) c[q] = 0ull;
+  // Depth, mask and colour are loaded without a branch (pixels outside the
+  // level read pixel 0; a missing mask reads the colour plane) so the loads
+  // share one round trip and are first used after the solve.
+  const bool inside = ul < wl && vl < hl;
+  const int u = inside ? ul << lv : 0, v = inside ? vl << lv : 0;
+  const int pix = v * f.W + u;
+  const float D = load_depth<DF>(f, pix);
+  const uint8_t mk_raw = (mask ? mask : f.rgb)[pix];
+  const uint8_t* px = f.rgb + 3 * pix;
+  const uint8_t c0 = px[0], c1 = px[1], c2 = px[2];
+  if (a.acc_clear >= 0) {
+    // the workgroups of the job share the clearing of the used chunk words
+    const int ng = b.base[jb + 1] - b.base[jb];
+    const int per = (kUsedWords + ng - 1) / ng;
+    const int q1 = min(g0 * per + per, kUsedWords);
+    for (int q = g0 * per + threadIdx.x; q < q1; q += kTrackBlock) *used_word(acc_buf(m, a.acc_clear), q) = 0ull;
   }
   if (threadIdx.x < 64) {
     if (a.solve) {
@@ -305,7 +322,8 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   float term[kTerms];
 #pragma unroll
   for (int k = 0; k < kTerms; ++k) term[k] = 0.0f;
-  if (live) {
+  if (inside && depth_ok(D, m.dmax) && !(mask && mk_raw)) {
+    const float Ipix = luminance((float)c0, (float)c1, (float)c2);
     float R[9], t[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -400,8 +418,10 @@ __global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a
 
 __global__ void track_reset_kernel(Batch b) {
   const Job& J = b.job[blockIdx.x];
-  unsigned long long* acc = acc_buf(J.m, 0);
-  for (int q = threadIdx.x; q < 3 * kBufWords; q += blockDim.x) acc[q] = 0ull;
+  for (int bi = 0; bi < 3; ++bi) {
+    unsigned long long* acc = acc_buf(J.m, bi);
+    for (int q = threadIdx.x; q < kUsedWords; q += blockDim.x) *used_word(acc, q) = 0ull;
+  }
   if (threadIdx.x == 0) {
     J.m.st->track_stop = 0;
     J.m.st->track_counter = 0;

@@ -1,23 +1,47 @@
 """Helpers for rocprofv3 measurements of the library's kernels.
 
-  python -m paper_1905_02082_amd.profiling copy --mib 1024
+  python paper_1905_02082_amd/profiling.py copy --mib 1024
       runs a plain device-to-device copy of a known size (the calibration
-      kernel for the FETCH_SIZE / WRITE_SIZE counters: it must read and write
-      exactly mib MiB).
-  python -m paper_1905_02082_amd.profiling summary DIR [--kernel REGEX]
-      prints per-kernel call counts and durations (and per-dispatch PMC
-      values, when the run collected counters) from the rocprofv3 database
-      found under DIR.
+      kernel for the FETCH_SIZE / WRITE_SIZE counters: it reads and writes
+      exactly mib MiB per copy).
+  python -m paper_1905_02082_amd.profiling summary DIR [--kernel REGEX] [--by-grid]
+      prints per-kernel call counts and durations (optionally split by grid
+      size, e.g. per pyramid level) from the rocprofv3 database under DIR.
+  python -m paper_1905_02082_amd.profiling pmc --fetch DIR --write DIR
+         --copy-fetch DIR --copy-write DIR --kernel REGEX --skip N
+         [--copy-mib 1024] [--json OUT --name KERNEL --workload W --storage S]
+      HBM bytes per dispatch of the kernels matching REGEX: FETCH_SIZE and
+      WRITE_SIZE (KiB per dispatch, each from its own rocprofv3 --pmc run)
+      scaled by the factor that makes the same counter read the known size of
+      the calibration copy; the first N matching dispatches are skipped
+      (warmup).  With --json, writes the figure with the hash of the kernel's
+      sources, so a later edit of the kernel invalidates it.
 """
 from __future__ import annotations
 
 import argparse
 import glob
+import hashlib
+import json
 import os
 import re
 import sqlite3
 import statistics
 import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# sources whose text determines each measured kernel
+KERNEL_SOURCES = {"integrate_kernel": ("rf_fusion.hip", "rf_device.h", "rf_internal.h"),
+                  "track_kernel": ("rf_track.hip", "rf_device.h", "rf_internal.h")}
+
+
+def kernel_source_hash(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def copy_kernel(mib: int, reps: int = 5):
@@ -40,32 +64,63 @@ def _db(path):
     return sqlite3.connect(dbs[-1])
 
 
-def summary(path, kernel=None, out=sys.stdout):
+def summary(path, kernel=None, by_grid=False, out=sys.stdout):
     c = _db(path)
-    rows = list(c.execute("select name, duration, grid_x, workgroup_x, id from kernels"))
+    rows = list(c.execute("select name, duration, grid_x, workgroup_x from kernels order by start"))
     by = {}
-    for name, dur, gx, wx, kid in rows:
+    for name, dur, gx, wx in rows:
         if kernel and not re.search(kernel, name):
             continue
-        by.setdefault(name, []).append(dur)
-    print("%-72s %7s %12s %10s %10s" % ("kernel", "calls", "total_us", "avg_us", "median_us"), file=out)
-    for name, d in sorted(by.items(), key=lambda kv: -sum(kv[1])):
-        print("%-72s %7d %12.1f %10.2f %10.2f" % (name[:72], len(d), sum(d) / 1e3, sum(d) / len(d) / 1e3,
-                                                    statistics.median(d) / 1e3), file=out)
-    # per-dispatch counters, if the run collected any
-    try:
-        rows = list(c.execute("select kernel_name, counter_name, value from counters_collection"))
-    except sqlite3.Error:
-        rows = []
-    if rows:
-        vals = {}
-        for name, ctr, v in rows:
-            if kernel and not re.search(kernel, str(name)):
-                continue
-            vals.setdefault((str(name)[:60], ctr), []).append(float(v))
-        print("\nper-dispatch counters (mean over dispatches):", file=out)
-        for (name, ctr), v in sorted(vals.items()):
-            print("  %-60s %-12s n=%-5d mean=%.1f" % (name, ctr, len(v), sum(v) / len(v)), file=out)
+        key = (name, gx // max(wx, 1)) if by_grid else (name, None)
+        by.setdefault(key, []).append(dur)
+    print("%-64s %8s %7s %12s %10s %10s" % ("kernel", "groups", "calls", "total_us", "avg_us", "median_us"),
+          file=out)
+    for (name, g), d in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        print("%-64s %8s %7d %12.1f %10.2f %10.2f" % (name[:64], "" if g is None else g, len(d), sum(d) / 1e3,
+                                                       sum(d) / len(d) / 1e3, statistics.median(d) / 1e3),
+              file=out)
+
+
+def _counter(path, counter, kernel):
+    """Per-dispatch values (dispatch order) of one counter for kernels matching the regex."""
+    c = _db(path)
+    rows = list(c.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection"))
+    vals = {}
+    for did, name, ctr, v in rows:
+        if ctr == counter and re.search(kernel, str(name)):
+            vals[did] = vals.get(did, 0.0) + float(v)
+    return [vals[k] for k in sorted(vals)]
+
+
+def calibration(path, counter, mib):
+    """Factor that makes `counter` read the known bytes of the calibration copy."""
+    v = _counter(path, counter, r"copyBuffer|copy_kernel|direct_copy")
+    if not v:
+        raise SystemExit("no copy dispatch under %s" % path)
+    kib = statistics.median(v)
+    return (mib * 1024.0) / kib, kib
+
+
+def pmc(args):
+    f_fetch, k_fetch = calibration(args.copy_fetch, "FETCH_SIZE", args.copy_mib)
+    f_write, k_write = calibration(args.copy_write, "WRITE_SIZE", args.copy_mib)
+    fe = _counter(args.fetch, "FETCH_SIZE", args.kernel)[args.skip:]
+    wr = _counter(args.write, "WRITE_SIZE", args.kernel)[args.skip:]
+    if not fe or not wr:
+        raise SystemExit("no matching dispatches after skipping %d" % args.skip)
+    fetch_b = statistics.mean(fe) * 1024.0 * f_fetch
+    write_b = statistics.mean(wr) * 1024.0 * f_write
+    res = {"kernel": args.name or args.kernel, "dispatches": [len(fe), len(wr)],
+           "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
+           "hbm_bytes_per_launch": round(fetch_b + write_b),
+           "calibration": {"copy_mib": args.copy_mib, "fetch_kib_read": k_fetch, "fetch_factor": round(f_fetch, 4),
+                           "write_kib_read": k_write, "write_factor": round(f_write, 4)}}
+    if args.json:
+        res.update({"workload": args.workload, "storage": args.storage,
+                    "kernel_source_hash": kernel_source_hash(args.name)})
+        with open(args.json, "w") as fh:
+            json.dump(res, fh, indent=1)
+    print(json.dumps(res))
 
 
 def main():
@@ -77,11 +132,24 @@ def main():
     s = sub.add_parser("summary")
     s.add_argument("dir")
     s.add_argument("--kernel", default=None)
+    s.add_argument("--by-grid", action="store_true")
+    p = sub.add_parser("pmc")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    p.add_argument("--kernel", required=True)
+    p.add_argument("--skip", type=int, default=0)
+    p.add_argument("--copy-mib", type=int, default=1024)
+    p.add_argument("--json", default=None)
+    p.add_argument("--name", default=None, choices=sorted(KERNEL_SOURCES))
+    p.add_argument("--workload", default=None)
+    p.add_argument("--storage", default=None)
     args = ap.parse_args()
     if args.cmd == "copy":
         copy_kernel(args.mib, args.reps)
+    elif args.cmd == "summary":
+        summary(args.dir, args.kernel, args.by_grid)
     else:
-        summary(args.dir, args.kernel)
+        pmc(args)
 
 
 if __name__ == "__main__":
