@@ -117,6 +117,15 @@ rf_status run_batches(const rf_job* jobs, int32_t n, const char* what, Fill fill
     for (int32_t k = 0; k < i; ++k)
       if (jobs[k].map == jobs[i].map) return fail(RF_EINVAL, "%s: map of job %d appears twice", what, i);
   }
+  // every job is checked before anything is enqueued
+  std::vector<rf::Job> prepared(n);
+  for (int32_t k = 0; k < n; ++k) {
+    rf::FrameDev fd;
+    make_frame(&jobs[k].frame, fd);
+    prepared[k] = base_job(jobs[k].map, fd);
+    rf_status st = fill(jobs[k], prepared[k]);
+    if (st) return st;
+  }
   std::vector<int> done(n, 0);
   for (int32_t i = 0; i < n; ++i) {
     if (done[i]) continue;
@@ -125,12 +134,7 @@ rf_status run_batches(const rf_job* jobs, int32_t n, const char* what, Fill fill
     b.n = 0;
     for (int32_t k = i; k < n; ++k) {
       if (done[k] || jobs[k].frame.depth_format != df || jobs[k].map->h.p.storage != sto) continue;
-      rf::FrameDev fd;
-      make_frame(&jobs[k].frame, fd);
-      rf::Job J = base_job(jobs[k].map, fd);
-      rf_status st = fill(jobs[k], J);
-      if (st) return st;
-      b.job[b.n++] = J;
+      b.job[b.n++] = prepared[k];
       done[k] = 1;
       if (b.n == rf::kMaxBatch) {
         launch(b, df, sto);

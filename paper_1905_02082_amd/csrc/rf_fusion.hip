@@ -17,22 +17,21 @@
 
 namespace rf {
 
-// True for exactly one active lane per distinct key among the lanes with
-// valid set (wavefront-level de-duplication: neighbouring rays visit the same
-// blocks, and only one of them needs to probe, insert or stamp a block).
-__device__ __forceinline__ bool wave_first_of_key(unsigned long long key, bool valid) {
+// False when the lane just below holds the same key (and is active with a
+// valid cell): of a run of equal keys on consecutive lanes only the first
+// probes, inserts and stamps.  Neighbouring rays (consecutive pixels or
+// carve-grid pixels) mostly visit the same blocks in the same order, so this
+// removes most duplicates for a few instructions; duplicates that remain are
+// harmless (the CAS insert and the stamp exchange resolve them).
+__device__ __forceinline__ bool leads_run(unsigned long long key, bool valid, unsigned long long active) {
   const int lane = threadIdx.x & 63;
-  unsigned long long todo = __ballot(valid);
-  bool leader = false;
-  while (todo) {
-    const int l = __ffsll((long long)todo) - 1;
-    const unsigned int klo = __builtin_amdgcn_readlane((unsigned int)key, l);
-    const unsigned int khi = __builtin_amdgcn_readlane((unsigned int)(key >> 32), l);
-    const unsigned long long k = ((unsigned long long)khi << 32) | klo;
-    todo &= ~__ballot(valid && key == k);
-    leader |= (lane == l);
-  }
-  return leader;
+  const unsigned long long vmask = __ballot(valid) & active;
+  const int src = lane > 0 ? lane - 1 : 0;
+  const unsigned int klo = (unsigned int)__shfl((int)(unsigned int)key, src, 64);
+  const unsigned int khi = (unsigned int)__shfl((int)(unsigned int)(key >> 32), src, 64);
+  const bool below_same = lane > 0 && ((vmask >> (lane - 1)) & 1ull) &&
+                          ((((unsigned long long)khi << 32) | klo) == key);
+  return valid && !below_same;
 }
 
 // Block-grid DDA of segment q0 -> q1 (block units): cells c = floor(q0) ...
@@ -147,10 +146,11 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
     unsigned long long key[kBatch];
     uint32_t hb[kBatch];
     Bucket bk[kBatch];
+    const unsigned long long active = __ballot(true);
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
       key[q] = pack_key(cx[q], cy[q], cz[q]);
-      ok[q] = wave_first_of_key(key[q], ok[q]);
+      ok[q] = leads_run(key[q], ok[q], active);
       if (!ok[q]) continue;
       hb[q] = hash3(cx[q], cy[q], cz[q]) & m.bucket_mask;
       bk[q] = m.buckets[hb[q]];
