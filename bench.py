@@ -228,7 +228,7 @@ def main():
     seq = make_sequence(args.workload, n)
     log("rendered %d frames %dx%d in %.1f s" % (n, seq.width, seq.height, time.perf_counter() - t0))
 
-    max_blocks = {"static_room": 1 << 18, "dynamic_room": 1 << 18, "large_rooms": 1 << 22}[args.workload]
+    max_blocks = {"static_room": 1 << 18, "dynamic_room": 1 << 18, "large_rooms": 3 << 20}[args.workload]
     mp = rf.MapParams(seq.voxel_size, seq.truncation, seq.depth_max, seq.num_buckets, max_blocks, 255,
                       seq.carve_stride, args.storage, seq.width * seq.height)
     tp = rf.TrackParams(seq.levels, seq.iters, 0.025, 64, 0.0)
