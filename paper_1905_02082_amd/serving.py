@@ -15,7 +15,9 @@ arrival process).  The server loop:
     the GPU runs step n; a session's consecutive frames stay ordered on the
     stream;
   * records a completion event per step and measures each frame's latency
-    from its arrival time to that event.
+    from its arrival time to that event (and, separately, from the later of
+    its arrival and its session's admission, which leaves out the time a
+    session waited for memory).
 
 Results do not depend on how frames were batched (every job's arithmetic is
 independent of its neighbours), which tests/test_gpu_batch.py checks.
@@ -64,6 +66,7 @@ class ServeResult:
     frames: int
     wall_s: float
     latencies_ms: np.ndarray
+    admitted_latencies_ms: np.ndarray
     steps: int
     mean_batch: float
     peak_sessions: int
@@ -76,11 +79,14 @@ class ServeResult:
         return self.frames / self.wall_s
 
     def summary(self):
-        lat = self.latencies_ms
+        lat, adm = self.latencies_ms, self.admitted_latencies_ms
         return {"frames": self.frames, "wall_s": round(self.wall_s, 3), "frames_per_s": round(self.fps, 2),
                 "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                                "p99": round(float(np.percentile(lat, 99)), 3),
                                "max": round(float(lat.max()), 3)},
+                "latency_after_admission_ms": {"p50": round(float(np.percentile(adm, 50)), 3),
+                                               "p99": round(float(np.percentile(adm, 99)), 3),
+                                               "max": round(float(adm.max()), 3)},
                 "steps": self.steps, "mean_batch": round(self.mean_batch, 2),
                 "peak_sessions": self.peak_sessions, "peak_hbm_gib": round(self.peak_bytes / 2**30, 3),
                 "sessions_that_waited_for_memory": self.admitted_late,
@@ -88,10 +94,11 @@ class ServeResult:
 
 
 class _Live:
-    def __init__(self, spec: SessionSpec, session: Session, nbytes: int):
+    def __init__(self, spec: SessionSpec, session: Session, nbytes: int, admitted: float):
         self.spec = spec
         self.session = session
         self.nbytes = nbytes
+        self.admitted = admitted  # seconds since the server started
         self.next = 0          # next frame to submit
         self.done = 0          # frames completed
 
@@ -122,6 +129,7 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
     late = 0
     inflight = []            # (event, [(live, arrival_s, pixels)], frame tensors)
     latencies = []
+    admitted_latencies = []
     per_res = {}
     n_steps = 0
     batch_sizes = []
@@ -145,6 +153,7 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
             for lv, arr, key in members:
                 ms = (t_done - arr) * 1000.0
                 latencies.append(ms)
+                admitted_latencies.append((t_done - max(arr, lv.admitted)) * 1000.0)
                 per_res.setdefault(key, []).append(ms)
                 lv.done += 1
                 completed += 1
@@ -162,7 +171,7 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
             if t - spec.arrivals[0] > 1.0 / 30.0:
                 late += 1
             s = Session(spec.params, spec.seq.poses[spec.order[0]], dev)
-            live.append(_Live(spec, s, nb))
+            live.append(_Live(spec, s, nb, t))
             used += nb
             peak_bytes = max(peak_bytes, used)
         peak_sessions = max(peak_sessions, len(live))
@@ -211,5 +220,5 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
     lat = np.asarray(latencies)
     pr = {k: {"frames": len(v), "p50_ms": round(float(np.percentile(v, 50)), 3),
               "p99_ms": round(float(np.percentile(v, 99)), 3)} for k, v in sorted(per_res.items())}
-    return ServeResult(total, wall, lat, n_steps, float(np.mean(batch_sizes)) if batch_sizes else 0.0,
+    return ServeResult(total, wall, lat, np.asarray(admitted_latencies), n_steps, float(np.mean(batch_sizes)) if batch_sizes else 0.0,
                        peak_sessions, peak_bytes, late, pr)
