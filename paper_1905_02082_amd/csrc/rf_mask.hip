@@ -112,10 +112,10 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
   __syncthreads();
   // Local fixpoint.  A parallel pass over all pixels (every non-member checks
   // its 8 neighbours) doubles as the convergence test; while it still finds
-  // new members, wavefront 0 runs four directional sweeps (left to right,
-  // right to left, top to bottom, bottom to top): lane t walks line t and
-  // each step checks the three neighbours on the side already swept, so one
-  // sweep carries a path that is monotone in its direction across the tile.
+  // new members, four directional sweeps run (left to right, right to left,
+  // top to bottom, bottom to top): lane t walks line t and each step checks
+  // the three neighbours on the side already swept, so one sweep carries a
+  // path that is monotone in its direction across the tile.
   for (;;) {
     if (threadIdx.x == 0) *s_flag = 0;
     __syncthreads();
@@ -148,35 +148,49 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
     const int again = *s_flag;
     __syncthreads();
     if (!again) break;
-    if (threadIdx.x < 64) {
-      const int t = threadIdx.x;
+    // Wavefront w (0..3) sweeps direction w; lane t walks line t.  The three
+    // neighbours on the swept side are the lane's own previous cell and its
+    // two neighbouring lanes' previous cells, taken from registers by
+    // shuffles (the halo lines from LDS), so a step costs no LDS round trip.
+    // The four sweeps run concurrently: growth is monotone and the check
+    // above runs again after them, so the fixpoint is the same.
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    if (w < 4 && t < kTile) {
+      const int along = (w < 2) ? 1 : kHalo;   // next cell along the line
+      const int across = (w < 2) ? kHalo : 1;  // next line
+      const int sgn = (w & 1) ? -1 : 1;
+      int c = (1 + t) * across + (1 + ((w & 1) ? kTile - 1 : 0)) * along;
+      int cp = c - sgn * along;  // previous cell: the halo
+      uint32_t pm = s_m[cp];
+      float pd = s_d[cp];
 #pragma unroll 1
-      for (int dir = 0; dir < 4; ++dir) {
-        const int back = (dir == 0) ? -1 : (dir == 1) ? 1 : (dir == 2) ? -kHalo : kHalo;
-        const int side = (dir < 2) ? kHalo : 1;
-#pragma unroll 1
-        for (int step = 0; step < kTile; ++step) {
-          if (t < kTile) {
-            const int i = (dir & 1) ? (kTile - 1 - step) : step;
-            const int c = (dir < 2) ? (1 + t) * kHalo + (1 + i) : (1 + i) * kHalo + (1 + t);
-            const float dq = s_d[c];
-            if (!s_m[c] && dq > 0.0f) {
-              bool join = false;
-#pragma unroll
-              for (int o = -1; o <= 1; ++o) {
-                const int n = c + back + o * side;
-                if (s_m[n]) {
-                  const float dp = s_d[n];
-                  join |= fabsf(dp - dq) < theta * dp;
-                }
-              }
-              if (join) s_m[c] = 1;
-            }
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int i = 0; i < kTile; ++i) {
+        uint32_t cm = s_m[c];
+        const float cd = s_d[c];
+        uint32_t um = (uint32_t)__shfl((int)pm, t > 0 ? t - 1 : 0, 64);
+        float ud = __shfl(pd, t > 0 ? t - 1 : 0, 64);
+        uint32_t dm = (uint32_t)__shfl((int)pm, t < kTile - 1 ? t + 1 : t, 64);
+        float dd = __shfl(pd, t < kTile - 1 ? t + 1 : t, 64);
+        if (t == 0) {
+          um = s_m[cp - across];
+          ud = s_d[cp - across];
         }
+        if (t == kTile - 1) {
+          dm = s_m[cp + across];
+          dd = s_d[cp + across];
+        }
+        if (!cm && cd > 0.0f) {
+          const bool join = (pm && fabsf(pd - cd) < theta * pd) || (um && fabsf(ud - cd) < theta * ud) ||
+                            (dm && fabsf(dd - cd) < theta * dd);
+          if (join) {
+            s_m[c] = 1;
+            cm = 1;
+          }
+        }
+        pm = cm;
+        pd = cd;
+        cp = c;
+        c += sgn * along;
       }
     }
     __syncthreads();

@@ -6,7 +6,9 @@ arrival process).  The server loop:
 
   * admits waiting sessions while the HBM budget allows (a session's arena
     size is known exactly from hashmap_bytes) and frees a session's map when
-    its last frame completes, so later sessions take its place;
+    its last frame completes, so later sessions take its place; a session
+    that had to wait starts streaming when it is admitted (its frames'
+    arrival times move by the wait, which is reported separately);
   * forms each step from every admitted session that has an arrived frame
     (oldest frames first, up to max_batch) and runs the step as one launch set
     per stage over all of them (process_batch), uploading the frames from
@@ -15,9 +17,7 @@ arrival process).  The server loop:
     the GPU runs step n; a session's consecutive frames stay ordered on the
     stream;
   * records a completion event per step and measures each frame's latency
-    from its arrival time to that event (and, separately, from the later of
-    its arrival and its session's admission, which leaves out the time a
-    session waited for memory).
+    from its arrival time to that event.
 
 Results do not depend on how frames were batched (every job's arithmetic is
 independent of its neighbours), which tests/test_gpu_batch.py checks.
@@ -66,7 +66,7 @@ class ServeResult:
     frames: int
     wall_s: float
     latencies_ms: np.ndarray
-    admitted_latencies_ms: np.ndarray
+    admission_waits_ms: np.ndarray   # per session: admission time - first scheduled arrival
     steps: int
     mean_batch: float
     peak_sessions: int
@@ -79,14 +79,14 @@ class ServeResult:
         return self.frames / self.wall_s
 
     def summary(self):
-        lat, adm = self.latencies_ms, self.admitted_latencies_ms
+        lat, adm = self.latencies_ms, self.admission_waits_ms
         return {"frames": self.frames, "wall_s": round(self.wall_s, 3), "frames_per_s": round(self.fps, 2),
                 "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                                "p99": round(float(np.percentile(lat, 99)), 3),
                                "max": round(float(lat.max()), 3)},
-                "latency_after_admission_ms": {"p50": round(float(np.percentile(adm, 50)), 3),
-                                               "p99": round(float(np.percentile(adm, 99)), 3),
-                                               "max": round(float(adm.max()), 3)},
+                "admission_wait_ms": {"p50": round(float(np.percentile(adm, 50)), 3),
+                                      "p99": round(float(np.percentile(adm, 99)), 3),
+                                      "max": round(float(adm.max()), 3)},
                 "steps": self.steps, "mean_batch": round(self.mean_batch, 2),
                 "peak_sessions": self.peak_sessions, "peak_hbm_gib": round(self.peak_bytes / 2**30, 3),
                 "sessions_that_waited_for_memory": self.admitted_late,
@@ -94,13 +94,16 @@ class ServeResult:
 
 
 class _Live:
-    def __init__(self, spec: SessionSpec, session: Session, nbytes: int, admitted: float):
+    def __init__(self, spec: SessionSpec, session: Session, nbytes: int, shift: float):
         self.spec = spec
         self.session = session
         self.nbytes = nbytes
-        self.admitted = admitted  # seconds since the server started
-        self.next = 0          # next frame to submit
-        self.done = 0          # frames completed
+        self.shift = shift      # admission wait: the session's arrivals move by it
+        self.next = 0           # next frame to submit
+        self.done = 0           # frames completed
+
+    def arrival(self, k):
+        return float(self.spec.arrivals[k]) + self.shift
 
 
 def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget: int, max_batch=64, depth=2,
@@ -129,7 +132,7 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
     late = 0
     inflight = []            # (event, [(live, arrival_s, pixels)], frame tensors)
     latencies = []
-    admitted_latencies = []
+    waits = []
     per_res = {}
     n_steps = 0
     batch_sizes = []
@@ -153,7 +156,6 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
             for lv, arr, key in members:
                 ms = (t_done - arr) * 1000.0
                 latencies.append(ms)
-                admitted_latencies.append((t_done - max(arr, lv.admitted)) * 1000.0)
                 per_res.setdefault(key, []).append(ms)
                 lv.done += 1
                 completed += 1
@@ -168,16 +170,18 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
             if used + nb > hbm_budget:
                 break
             waiting.pop(0)
-            if t - spec.arrivals[0] > 1.0 / 30.0:
+            shift = max(0.0, t - float(spec.arrivals[0]))
+            if shift > 1.0 / 30.0:
                 late += 1
+            waits.append(shift * 1000.0)
             s = Session(spec.params, spec.seq.poses[spec.order[0]], dev)
-            live.append(_Live(spec, s, nb, t))
+            live.append(_Live(spec, s, nb, shift))
             used += nb
             peak_bytes = max(peak_bytes, used)
         peak_sessions = max(peak_sessions, len(live))
         # step: admitted sessions with an arrived, unsubmitted frame, oldest first
-        ready = [lv for lv in live if lv.next < len(lv.spec.arrivals) and lv.spec.arrivals[lv.next] <= t]
-        ready.sort(key=lambda lv: lv.spec.arrivals[lv.next])
+        ready = [lv for lv in live if lv.next < len(lv.spec.arrivals) and lv.arrival(lv.next) <= t]
+        ready.sort(key=lambda lv: lv.arrival(lv.next))
         ready = ready[:max_batch]
         if ready and len(inflight) < depth:
             frames, members, keep = [], [], []
@@ -189,7 +193,7 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
                 cd = ch.to(dev, non_blocking=True)
                 keep += [dd, cd]
                 frames.append(Frame(dd, cd, *seq.intrinsics, depth_scale=seq.depth_scale))
-                members.append((lv, float(lv.spec.arrivals[lv.next]), "%dx%d" % (seq.width, seq.height)))
+                members.append((lv, lv.arrival(lv.next), "%dx%d" % (seq.width, seq.height)))
                 lv.next += 1
             process_batch([lv.session for lv in ready], frames, tp, mp, dynamic, stream)
             ev = torch.cuda.Event(enable_timing=True)
@@ -202,7 +206,7 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
                 retire(block=len(inflight) >= depth or not ready)
             elif not ready:
                 # idle until the next arrival (or admission retry)
-                nxt = [lv.spec.arrivals[lv.next] for lv in live if lv.next < len(lv.spec.arrivals)]
+                nxt = [lv.arrival(lv.next) for lv in live if lv.next < len(lv.spec.arrivals)]
                 if waiting:
                     nxt.append(waiting[0].arrivals[0])
                 if nxt:
@@ -220,5 +224,5 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
     lat = np.asarray(latencies)
     pr = {k: {"frames": len(v), "p50_ms": round(float(np.percentile(v, 50)), 3),
               "p99_ms": round(float(np.percentile(v, 99)), 3)} for k, v in sorted(per_res.items())}
-    return ServeResult(total, wall, lat, np.asarray(admitted_latencies), n_steps, float(np.mean(batch_sizes)) if batch_sizes else 0.0,
+    return ServeResult(total, wall, lat, np.asarray(waits), n_steps, float(np.mean(batch_sizes)) if batch_sizes else 0.0,
                        peak_sessions, peak_bytes, late, pr)
