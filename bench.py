@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="serving: admission budget")
     ap.add_argument("--max-batch", type=int, default=64, help="serving: sessions per step")
     ap.add_argument("--unpaced", action="store_true", help="serving: all frames available at once")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="sessions processed together per step (1..8; the same scene at staggered frames)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for cpu_baseline")
     args = ap.parse_args()
@@ -220,13 +222,16 @@ def main():
         args.storage = "fp32"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    W, K = args.warmup, args.steps
+    W, K, B = args.warmup, args.steps, args.batch
     n = W + K
     if W < 1:
         raise SystemExit("--warmup must be >= 1 (frame 0 initialises the map)")
+    if not 1 <= B <= 8:
+        raise SystemExit("--batch must be in [1, 8]")
+    offset = 25  # session i starts at frame i * offset of the same rendered sequence
     t0 = time.perf_counter()
-    seq = make_sequence(args.workload, n)
-    log("rendered %d frames %dx%d in %.1f s" % (n, seq.width, seq.height, time.perf_counter() - t0))
+    seq = make_sequence(args.workload, n + offset * (B - 1))
+    log("rendered %d frames %dx%d in %.1f s" % (seq.n, seq.width, seq.height, time.perf_counter() - t0))
 
     max_blocks = {"static_room": 1 << 18, "dynamic_room": 1 << 18, "large_rooms": 3 << 20}[args.workload]
     mp = rf.MapParams(seq.voxel_size, seq.truncation, seq.depth_max, seq.num_buckets, max_blocks, 255,
@@ -234,68 +239,49 @@ def main():
     tp = rf.TrackParams(seq.levels, seq.iters, 0.025, 64, 0.0)
     mk = rf.MaskParams(0.5, 0.007)
     frames = [rf.Frame.from_numpy(seq.depth[k], seq.rgb[k], *seq.intrinsics, depth_scale=seq.depth_scale,
-                                  device=dev) for k in range(n)]
-    m = rf.Map(mp, dev)
-    pose = torch.as_tensor(seq.poses[0]).to(dev).contiguous()
-    mask = torch.zeros((seq.height, seq.width), dtype=torch.uint8, device=dev)
-    stats = torch.zeros(16, dtype=torch.float64, device=dev)
+                                  device=dev) for k in range(seq.n)]
+    sessions = [rf.Session(mp, seq.poses[offset * i], dev) for i in range(B)]
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
     stage_names = ["track1", "mask", "track2", "allocate", "integrate"]
 
-    def step(fr, ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        m.track(fr, pose, tp, None, stats)
-        if ev is not None:
-            ev[1].record(stream)
-        m.dynamic_mask(fr, pose, mk, out=mask)
-        if ev is not None:
-            ev[2].record(stream)
-        m.track(fr, pose, tp, mask, stats)
-        if ev is not None:
-            ev[3].record(stream)
-        m.allocate(fr, pose, mask)
-        if ev is not None:
-            ev[4].record(stream)
-        m.integrate(fr, pose, mask)
-        if ev is not None:
-            ev[5].record(stream)
+    def step(k, ev=None):
+        rf.process_batch(sessions, [frames[offset * i + k] for i in range(B)], tp, mk, True, stream, ev)
 
-    # frame 0 initialises the map at its given pose; frames 1..W-1 warm up
-    m.allocate(frames[0], pose)
-    m.integrate(frames[0], pose)
-    for k in range(1, W):
-        step(frames[k])
+    # frame 0 initialises each map at its given pose; frames 1..W-1 warm up
+    for k in range(W):
+        step(k)
     torch.cuda.synchronize()
-    c0 = m.cumulative_counts()
+    c0 = np.sum([s.map.cumulative_counts() for s in sessions], axis=0)
 
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(K):
-        step(frames[W + i], events[i])
+        step(W + i, events[i])
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    c1 = m.cumulative_counts()
-    flags, nblocks = m.status()
+    c1 = np.sum([s.map.cumulative_counts() for s in sessions], axis=0)
+    status = [s.map.status() for s in sessions]
+    flags = int(np.bitwise_or.reduce([f for f, _ in status]))
+    nblocks = int(status[0][1])
 
     wall = t_end - t_start
     per_stage = np.array([[events[i][j].elapsed_time(events[i][j + 1]) for j in range(5)] for i in range(K)])
     frame_ms = np.array([events[i][0].elapsed_time(events[i][5]) for i in range(K)])
-    fps = K / wall
-    T_final = pose.cpu().numpy()
+    fps = B * K / wall
+    T_final = sessions[0].pose.cpu().numpy()
 
     # tracking roofline (the dominant kernel): algorithmic bytes per sweep from
     # the host footprint of sampled frames; duration = tracking stage time /
     # sweeps (each pass is levels x iterations track_kernel launches plus one
     # reset and one finalize launch of a few microseconds, counted in)
-    keys = m.export()[0].cpu().numpy()
+    keys = sessions[0].map.export()[0].cpu().numpy()
     sample = list(range(W, n, max(1, K // 4)))[:4]
     fp1, pix = track_footprint(seq, keys, sample, args.storage)
     sweeps = seq.levels * seq.iters
-    track_alg = seq.iters * (2 * fp1.sum() + pix.sum()) / (2 * sweeps)
+    track_alg = B * seq.iters * (2 * fp1.sum() + pix.sum()) / (2 * sweeps)
     track_ms = float((per_stage[:, 0] + per_stage[:, 2]).mean()) / (2 * sweeps)
     track_achieved = track_alg / (track_ms * 1e-3) / 1e9
 
@@ -303,18 +289,19 @@ def main():
     band = c1[0] - c0[0]
     free = c1[1] - c0[1]
     blocks = c1[2] - c0[2]
-    launches = c1[3] - c0[3]
+    map_frames = c1[3] - c0[3]                               # maps x frames integrated
     rec = {"fp32": (8, 4), "fp16": (4, 4)}[args.storage]   # (sdf+weight, colour) bytes per voxel
     img = seq.width * seq.height * (2 + 1 + 3)              # depth u16 + mask u8 + RGB8
-    alg_bytes = (band * 2 * (rec[0] + rec[1]) + free * 2 * rec[0] + blocks * (4 + 16) + launches * img)
+    alg_bytes = (band * 2 * (rec[0] + rec[1]) + free * 2 * rec[0] + blocks * (4 + 16) + map_frames * img)
+    launches = K                                            # one integration launch per step
     alg_per_launch = alg_bytes / max(launches, 1)
     integ_ms = float(per_stage[:, 4].mean())
     achieved = alg_per_launch / (integ_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile("integrate_kernel", args.workload, args.storage)
-    track_traffic = traffic_from_profile("track_kernel", args.workload, args.storage)
+    traffic = traffic_from_profile("integrate_kernel", args.workload, args.storage) if B == 1 else None
+    track_traffic = traffic_from_profile("track_kernel", args.workload, args.storage) if B == 1 else None
 
     # trajectory error against the generator's ground truth (context only)
-    E = np.linalg.inv(seq.poses[n - 1]) @ T_final
+    E = np.linalg.inv(seq.poses[n - 1]) @ T_final       # session 0
     ate_last = float(np.linalg.norm(E[:3, 3]))
 
     out = {
@@ -324,17 +311,19 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(1000.0 * wall / K, 4),
+        "ms_per_step": round(1000.0 * wall / K, 4),     # one step = one frame of every session
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "%s %dx%d, %d frames, voxel %.3g m, truncation %.3g m, 8^3 blocks, 2^%d buckets, "
-                               "%d levels x %d GN iterations, %s storage, full dynamic pipeline per frame"
+                               "%d levels x %d GN iterations, %s storage, full dynamic pipeline per frame%s"
                                % (args.workload, seq.width, seq.height, n, seq.voxel_size, seq.truncation,
-                                  int(np.log2(seq.num_buckets)), seq.levels, seq.iters, args.storage),
-                   "frames": n, "width": seq.width, "height": seq.height, "storage": args.storage},
+                                  int(np.log2(seq.num_buckets)), seq.levels, seq.iters, args.storage,
+                                  "" if B == 1 else ", %d sessions per launch set" % B),
+                   "frames": n, "width": seq.width, "height": seq.height, "storage": args.storage,
+                   "sessions": B},
         "latency_ms": {"p50": round(float(np.percentile(frame_ms, 50)), 4),
                        "p99": round(float(np.percentile(frame_ms, 99)), 4)},
         "stages_ms": {nm: round(float(per_stage[:, j].mean()), 4) for j, nm in enumerate(stage_names)},
@@ -355,7 +344,7 @@ def main():
                      "blocks_per_launch": int(blocks / max(launches, 1))},
         "map": {"blocks": nblocks, "flags": flags, "final_position_error_m": round(ate_last, 5)},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and B == 1:
         v, sample = cpu_baseline(seq, args.cpu_budget)
         out["cpu_baseline"] = {"value": round(v, 5), "unit": "frames/s", "cores": 1, "kind": "oracle",
                                "sample": sample}

@@ -320,7 +320,7 @@ def _jobs(sessions, frames, mask=False, mask_out=False, stats=False):
     return arr
 
 
-def process_batch(sessions, frames, tp: TrackParams, mp: MaskParams, dynamic=True, stream=None):
+def process_batch(sessions, frames, tp: TrackParams, mp: MaskParams, dynamic=True, stream=None, events=None):
     """One step of the method for several sessions at once (one frame each),
     one launch set per stage (the paper's Fig. 2 order):
 
@@ -328,29 +328,48 @@ def process_batch(sessions, frames, tp: TrackParams, mp: MaskParams, dynamic=Tru
         -> block allocation -> integration
 
     A session's first frame is only allocated and integrated at its initial
-    pose.  Every result is the same as processing the session alone."""
+    pose.  Every result is the same as processing the session alone.
+    events: optional 6 torch.cuda.Event recorded on the stream before, between
+    and after the five stages (for timing)."""
     if len(sessions) != len(frames):
         raise RefusionError("one frame per session")
     L = N.load()
     st = _stream(stream)
+    tstream = stream if stream is not None else torch.cuda.current_stream()
+
+    def mark(i):
+        if events is not None:
+            events[i].record(tstream)
+
     run = [i for i, s in enumerate(sessions) if s.k > 0]
+    mark(0)
     if run:
         rs = [sessions[i] for i in run]
         rf_ = [frames[i] for i in run]
         tpc = tp.c()
         _check(L.track_frame_batch(_jobs(rs, rf_, stats=True), len(rs), ctypes.byref(tpc), st), "track_frame_batch")
+        mark(1)
         if dynamic:
             mpc = mp.c()
             _check(L.compute_dynamic_mask_batch(_jobs(rs, rf_, mask_out=True), len(rs), ctypes.byref(mpc), st),
                    "compute_dynamic_mask_batch")
+            mark(2)
             _check(L.track_frame_batch(_jobs(rs, rf_, mask=True, stats=True), len(rs), ctypes.byref(tpc), st),
                    "track_frame_batch")
+        else:
+            mark(2)
+    else:
+        mark(1)
+        mark(2)
+    mark(3)
     use_mask = [dynamic and s.k > 0 for s in sessions]
     jobs = _jobs(sessions, frames)
     for i, s in enumerate(sessions):
         jobs[i].d_mask = s.mask.data_ptr() if (use_mask[i] and s.mask is not None) else None
     _check(L.hashmap_allocate_batch(jobs, len(sessions), st), "hashmap_allocate_batch")
+    mark(4)
     _check(L.integrate_frame_batch(jobs, len(sessions), st), "integrate_frame_batch")
+    mark(5)
     for s in sessions:
         s.k += 1
 
