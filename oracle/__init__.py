@@ -58,6 +58,8 @@ def _load():
         "orc_normal_equations": (c_int, [c_void_p, P(_Frame), c_void_p, c_void_p, c_int, c_float, c_void_p]),
         "orc_track": (c_int, [c_void_p, P(_Frame), c_void_p, c_void_p, c_int, c_int, c_float, c_int,
                               c_double, c_void_p]),
+        "orc_track_lm": (c_int, [c_void_p, P(_Frame), c_void_p, c_void_p, c_int, c_int, c_float, c_int,
+                                 c_double, c_void_p, c_void_p]),
         "orc_mask": (c_int, [c_void_p, P(_Frame), c_void_p, c_float, c_float, c_void_p, c_void_p,
                              c_void_p, c_void_p, c_void_p]),
         "orc_export": (c_int64, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64]),
@@ -161,6 +163,20 @@ class OracleMap:
         flags = self.L.orc_track(self.h, ctypes.byref(fr.s), T.ctypes.data, _ptr(m), levels, iters, w_c,
                                  min_valid, lm_lambda, stats.ctypes.data)
         return T, int(flags), stats
+
+    def track_lm(self, fr: Frame, pose, levels=3, iters=10, w_c=0.025, min_valid=64, lambda0=1e-4,
+                 mask=None):
+        """Levenberg-Marquardt registration (Section III-B's solver; accept /
+        reject on the mean cost, lambda /10 and x10).  Returns (pose, flags,
+        stats, trace) with trace rows (level, mean cost, count, accepted,
+        lambda after the decision), one per evaluation."""
+        T = np.array(pose, np.float64, order="C")
+        m = _mask_arg(mask, fr)
+        stats = np.zeros(4 + levels, np.float64)
+        trace = np.zeros((levels * iters, 5), np.float64)
+        flags = self.L.orc_track_lm(self.h, ctypes.byref(fr.s), T.ctypes.data, _ptr(m), levels, iters, w_c,
+                                    min_valid, lambda0, stats.ctypes.data, trace.ctypes.data)
+        return T, int(flags), stats, trace
 
     def mask(self, fr: Frame, pose, gamma=0.5, theta=0.007):
         """Returns dict(raw, eroded, filled, final, residual) (FP32 mirror only)."""

@@ -786,6 +786,68 @@ int orc_track(void* p, const orc_frame* fr, double* T, const uint8_t* mask, int 
   return flags;
 }
 
+// Levenberg-Marquardt variant of the same coarse-to-fine registration (the
+// solver Section III-B names), in the order the GPU schedule evaluates it:
+// evaluation e (e = 0 .. levels*iters - 1, level by level) computes the normal
+// equations at the candidate pose C_e.  The first evaluation of each level is
+// accepted as it is (its cost is not comparable with the previous level's);
+// later ones are accepted when they have at least min_valid residuals and a
+// mean cost (cost / count) no larger than the accepted one's; then lambda is
+// divided by 10, and a rejected candidate multiplies it by 10 (at least 1e-4).
+// Unless e is the last evaluation, the next candidate is exp(delta^) T_a with
+// (H_a + lambda diag H_a) delta = -g_a from the accepted pose T_a and its
+// normal equations.  The result is the accepted pose after the last decision.
+// stats as orc_track, with stats[2] = accepted steps.  trace (nullable,
+// 5 doubles per evaluation): level, cost/count of C_e, count, accepted (0/1),
+// lambda after the decision.
+int orc_track_lm(void* p, const orc_frame* fr, double* T, const uint8_t* mask, int levels, int iters,
+                 float w_c, int min_valid, double lambda0, double* stats, double* trace) {
+  OrcMap* h = (OrcMap*)p;
+  Frame f = to_frame(fr);
+  double ne_c[29] = {0}, ne_a[29] = {0};
+  double Ta[16], C[16];
+  for (int i = 0; i < 16; ++i) Ta[i] = C[i] = T[i];
+  double lambda = lambda0;
+  int done = 0, flags = 0, e = 0;
+  const int total = levels * iters;
+  std::vector<double> first(levels, 0.0);
+  for (int l = levels - 1; l >= 0 && !flags; --l) {
+    for (int it = 0; it < iters; ++it, ++e) {
+      if (h->real_bits == 32) normal_equations(*as<float>(h->m), f, C, mask, l, w_c, ne_c);
+      else normal_equations(*as<double>(h->m), f, C, mask, l, w_c, ne_c);
+      bool accept;
+      if (it == 0) {
+        first[l] = ne_c[28];
+        accept = true;
+      } else {
+        accept = ne_c[28] >= min_valid && ne_c[27] / ne_c[28] <= ne_a[27] / ne_a[28];
+        lambda = accept ? lambda / 10.0 : std::max(lambda * 10.0, 1e-4);
+        if (accept) ++done;
+      }
+      if (accept) {
+        for (int i = 0; i < 29; ++i) ne_a[i] = ne_c[i];
+        for (int i = 0; i < 16; ++i) Ta[i] = C[i];
+      }
+      if (trace) {
+        double* t = trace + 5 * e;
+        t[0] = l; t[1] = ne_c[28] > 0 ? ne_c[27] / ne_c[28] : 0.0; t[2] = ne_c[28]; t[3] = accept; t[4] = lambda;
+      }
+      if (e == total - 1) break;
+      if (ne_a[28] < min_valid) { flags |= 1; break; }
+      double delta[6];
+      if (!solve6(ne_a, lambda, delta)) { flags |= 2; break; }
+      for (int i = 0; i < 16; ++i) C[i] = Ta[i];
+      pose_left_update(delta, C);
+    }
+  }
+  for (int i = 0; i < 16; ++i) T[i] = Ta[i];
+  if (stats) {
+    stats[0] = ne_a[27]; stats[1] = ne_a[28]; stats[2] = done; stats[3] = flags;
+    for (int l = 0; l < levels; ++l) stats[4+l] = first[l];
+  }
+  return flags;
+}
+
 int orc_mask(void* p, const orc_frame* fr, const double* T, float gamma, float theta, uint8_t* raw,
              uint8_t* eroded, uint8_t* filled, uint8_t* final_, float* residual) {
   OrcMap* h = (OrcMap*)p;

@@ -10,6 +10,7 @@ import scipy.ndimage
 from scipy.spatial.transform import Rotation
 
 import oracle as O
+import synth
 from synth import analytic as A
 
 
@@ -259,6 +260,81 @@ def test_tracking_recovers_known_rigid_transform():
         E = np.linalg.inv(pose) @ T
         assert np.linalg.norm(E[:3, 3]) < 1e-6
         assert np.linalg.norm(Rotation.from_matrix(E[:3, :3]).as_rotvec()) < 1e-6
+
+
+# --- Levenberg-Marquardt variant (the solver Section III-B names) --------------
+
+def test_lm_recovers_known_rigid_transform():
+    pose, depth, rgb, mp, K = corner_scene()
+    m = O.OracleMap(0.01, 0.1, real_bits=64)
+    m.import_(*mp)
+    fr = O.Frame(depth, rgb, *K)
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        xi = np.r_[rng.uniform(-0.03, 0.03, 3), np.radians(rng.uniform(-2, 2, 3))]
+        T, flags, st, trace = m.track_lm(fr, O.pose_left_update(xi, pose), levels=3, iters=15, w_c=0.0)
+        assert flags == 0
+        E = np.linalg.inv(pose) @ T
+        assert np.linalg.norm(E[:3, 3]) < 1e-6
+        assert np.linalg.norm(Rotation.from_matrix(E[:3, :3]).as_rotvec()) < 1e-6
+
+
+def test_lm_with_zero_lambda_takes_the_gauss_newton_step():
+    """lambda = 0: the first step is the Gauss-Newton step, so after one
+    accepted step LM and GN return the same pose."""
+    pose, depth, rgb, mp, K = corner_scene()
+    m = O.OracleMap(0.01, 0.1, real_bits=64)
+    m.import_(*mp)
+    fr = O.Frame(depth, rgb, *K)
+    T0 = O.pose_left_update(np.r_[0.01, -0.02, 0.015, 0.01, -0.02, 0.015], pose)
+    T_gn, _, _ = m.track(fr, T0, levels=1, iters=1, w_c=0.0)
+    T_lm, flags, st, trace = m.track_lm(fr, T0, levels=1, iters=2, w_c=0.0, lambda0=0.0)
+    assert flags == 0 and trace[1, 3] == 1.0
+    assert np.array_equal(T_lm, T_gn)
+
+
+def test_lm_step_solves_the_damped_system():
+    """With a large lambda the accepted step is delta = -(H + lambda diag H)^-1 g
+    from the normal equations at the start pose (solved here with numpy)."""
+    pose, depth, rgb, mp, K = corner_scene()
+    m = O.OracleMap(0.01, 0.1, real_bits=64)
+    m.import_(*mp)
+    fr = O.Frame(depth, rgb, *K)
+    T0 = O.pose_left_update(np.r_[0.02, 0.01, -0.01, 0.0, 0.02, 0.0], pose)
+    lam = 50.0
+    ne = m.normal_equations(fr, T0, level=0, w_c=0.0)
+    H = np.zeros((6, 6))
+    H[np.triu_indices(6)] = ne[:21]
+    H = H + np.triu(H, 1).T
+    delta = np.linalg.solve(H + lam * np.diag(np.diag(H)), -ne[21:27])
+    T_lm, flags, st, trace = m.track_lm(fr, T0, levels=1, iters=2, w_c=0.0, lambda0=lam)
+    assert flags == 0 and trace[1, 3] == 1.0 and trace[1, 1] < trace[0, 1]
+    np.testing.assert_allclose(T_lm, O.pose_left_update(delta, T0), rtol=0, atol=1e-12)
+
+
+def test_lm_never_returns_a_rejected_candidate():
+    """Once converged, candidates whose mean cost is not lower are rejected; a
+    rejected evaluation leaves the result unchanged (the run with one
+    evaluation less returns the same pose), an accepted one moves it, and
+    within a level the accepted mean cost never rises."""
+    seq = synth.parity_room(n_frames=3)
+    m = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=64)
+    for k in range(2):
+        fr = O.Frame(seq.depth[k], seq.rgb[k], *seq.intrinsics)
+        m.allocate(fr, seq.poses[k])
+        m.integrate(fr, seq.poses[k])
+    fr2 = O.Frame(seq.depth[2], seq.rgb[2], *seq.intrinsics)
+    T0 = O.pose_left_update(np.r_[0.02, -0.02, 0.015, 0.03, -0.02, 0.04], seq.poses[2])
+    n = 10
+    _, _, _, trace = m.track_lm(fr2, T0, levels=1, iters=n, lambda0=0.0)
+    acc = trace[:, 3] == 1
+    assert acc[0] and not acc.all(), "the case must contain a rejection"
+    costs = trace[acc, 1]
+    assert np.all(np.diff(costs) <= 0)
+    for e in range(1, n):
+        T_e, _, _, _ = m.track_lm(fr2, T0, levels=1, iters=e + 1, lambda0=0.0)
+        T_p, _, _, _ = m.track_lm(fr2, T0, levels=1, iters=e, lambda0=0.0)
+        assert np.array_equal(T_e, T_p) == (not acc[e]), e
 
 
 def test_tracking_flags_too_few_pixels():
