@@ -91,7 +91,14 @@ typedef struct {
   int32_t iters_per_level; /* Gauss-Newton / LM iterations per level (fixed count) */
   float w_c;               /* weight of the photometric term, Eq. 4 */
   int32_t min_valid;       /* fewer residuals stop the pass (RF_FLAG_TRACK_FEW_PIXELS) */
-  double lm_lambda;        /* damping: solves (H + lambda diag H) delta = -g; 0 = Gauss-Newton */
+  double lm_lambda;        /* damping: solves (H + lambda diag H) delta = -g; 0 = Gauss-Newton;
+                              with adaptive = 1 the starting lambda */
+  int32_t adaptive;        /* 0: every step is taken (Gauss-Newton, or fixed damping);
+                              1: Levenberg-Marquardt (Sec. III-B): the first evaluation of a level is
+                              accepted, a later candidate only with >= min_valid residuals and a mean
+                              cost (cost/count) no larger than the accepted one (lambda /= 10), else
+                              it is rejected (lambda = max(10 lambda, 1e-4)); steps start from the
+                              accepted pose; the result is the last accepted pose */
 } rf_track_params;
 
 typedef struct {

@@ -83,10 +83,12 @@ class TrackParams:
     iters_per_level: int = 10
     w_c: float = 0.025          # photometric weight (Table I)
     min_valid: int = 64
-    lm_lambda: float = 0.0      # 0: Gauss-Newton
+    lm_lambda: float = 0.0      # 0: Gauss-Newton; with adaptive, the starting lambda
+    adaptive: bool = False      # Levenberg-Marquardt accept / reject with adaptive lambda
 
     def c(self):
-        return N.RfTrackParams(self.levels, self.iters_per_level, self.w_c, self.min_valid, self.lm_lambda)
+        return N.RfTrackParams(self.levels, self.iters_per_level, self.w_c, self.min_valid, self.lm_lambda,
+                               1 if self.adaptive else 0)
 
 
 @dataclasses.dataclass

@@ -38,7 +38,7 @@ class RfMapParams(ctypes.Structure):
 
 class RfTrackParams(ctypes.Structure):
     _fields_ = [("levels", c_int32), ("iters_per_level", c_int32), ("w_c", c_float), ("min_valid", c_int32),
-                ("lm_lambda", c_double)]
+                ("lm_lambda", c_double), ("adaptive", c_int32)]
 
 
 class RfMaskParams(ctypes.Structure):

@@ -345,6 +345,7 @@ rf_status track_frame_batch(const rf_job* jobs, int32_t n, const rf_track_params
   if (tp->levels < 1 || tp->levels > 8 || tp->iters_per_level < 0 || tp->iters_per_level > 1000)
     return fail(RF_EINVAL, "levels must be in [1,8], iters_per_level in [0,1000]");
   if (!(tp->lm_lambda >= 0.0)) return fail(RF_EINVAL, "lm_lambda must be >= 0");
+  if (tp->adaptive != 0 && tp->adaptive != 1) return fail(RF_EINVAL, "adaptive must be 0 or 1");
   auto fill = [&](const rf_job& j, rf::Job& J) -> rf_status {
     J.pose = j.d_pose;
     J.mask = j.d_mask;

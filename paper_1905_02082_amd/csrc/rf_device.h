@@ -37,7 +37,8 @@ constexpr float kMaxVoxelCoord = 8.0e6f;   // |voxel coordinate| limit (8 x 2^20
 #endif
 constexpr int kTrackBlock = RF_TRACK_BLOCK;  // 256: 16x16 pixel tile; 512: 32x16
 constexpr int kAccCopies = RF_ACC_COPIES;    // copies of the tracking accumulators
-constexpr int kTrackScratchWords = 3 * kAccCopies * 29 * 16 + 32;  // 3 accumulator buffers + 2 poses
+// 3 accumulator buffers + 2 poses + 2 Levenberg-Marquardt states (48 words each)
+constexpr int kTrackScratchWords = 3 * kAccCopies * 29 * 16 + 32 + 2 * 48;
 constexpr int kNE = 29;                    // 21 H + 6 g + cost + count
 constexpr int kTile = 32;                  // flood-fill tile edge
 

@@ -46,6 +46,8 @@ struct TrackArgs {
   int acc_read, acc_write, acc_clear;  // accumulator buffer indices (-1: none)
   int pose_read, pose_write;           // 0/1: pose scratch, 2: caller's pose (-1: none)
   int mode;          // 0: track; 1: write the normal equations of acc_read to out29
+  int adaptive;      // 1: Levenberg-Marquardt (accept / reject, adaptive lambda); 0: fixed lambda
+  int state_read, state_write;         // Levenberg-Marquardt state buffers (0/1, -1: none)
 };
 
 __device__ __forceinline__ unsigned long long* acc_buf(const MapDev& m, int b) {
@@ -60,6 +62,12 @@ __device__ __forceinline__ unsigned long long* used_word(unsigned long long* buf
 }
 __device__ __forceinline__ double* pose_buf(const MapDev& m, double* user, int b) {
   return b == 2 ? user : reinterpret_cast<double*>(m.partials) + (size_t)3 * kBufWords + 16 * b;
+}
+// Levenberg-Marquardt state: [0, 16) accepted pose, [16, 45) its normal
+// equations, [45] lambda.
+constexpr int kLmWords = 48;
+__device__ __forceinline__ double* lm_state(const MapDev& m, int b) {
+  return reinterpret_cast<double*>(m.partials) + (size_t)3 * kBufWords + 32 + kLmWords * b;
 }
 
 // Adds v to a term: v 2^60 truncated toward zero as a 96-bit two's
@@ -216,24 +224,71 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
 // wavefront 0: reads the accumulated totals, solves, and (workgroup 0 only)
 // publishes the pose, the statistics and, on a degenerate system, the stop
 // flag.  Returns through LDS: s_T (new pose), *s_state.
+//
+// Levenberg-Marquardt (a.adaptive): the totals are those of the candidate
+// pose the previous launch evaluated.  The first evaluation of a level is
+// accepted as it is; a later one when it has at least min_valid residuals and
+// a mean cost (cost / count) no larger than the accepted one's, which divides
+// lambda by 10 (a rejection multiplies it by 10, at least 1e-4).  The step is
+// then solved from the accepted pose and its normal equations; with
+// final_only (the last decision of a pass) no step follows and the accepted
+// pose is the result.  s_nc, s_st: LDS scratch of kLmWords doubles each.
+template <bool LM>
 __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& a, rf_track_stats* stats,
-                           double* s_ne, double* s_T, int* s_state, bool publish, bool stopped) {
+                           double* s_ne, double* s_T, int* s_state, bool publish, bool stopped, bool final_only,
+                           double* s_nc, double* s_st) {
   const int lane = threadIdx.x;
+  const int ec = lane & 3;
   // the input pose is fetched together with the totals (one round trip)
   double tin[4] = {0.0, 0.0, 0.0, 0.0};
-  if (lane < 16) {
-    const double* Tin = pose_buf(m, user_pose, a.pose_read);
-    const int ec = lane & 3;
-    tin[0] = Tin[ec];
-    tin[1] = Tin[4 + ec];
-    tin[2] = Tin[8 + ec];
-    tin[3] = Tin[lane];
+  double lam = a.lm_lambda;
+  bool accept = true, first = true;
+  if (!LM) {
+    // the pose goes through LDS (fewer registers held across the solve)
+    if (lane < 16) s_nc[kNE + lane] = pose_buf(m, user_pose, a.pose_read)[lane];
+    if (lane < kNE) s_ne[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 16) {
+      tin[0] = s_nc[kNE + ec];
+      tin[1] = s_nc[kNE + 4 + ec];
+      tin[2] = s_nc[kNE + 8 + ec];
+      tin[3] = s_nc[kNE + lane];
+    }
+  } else {
+    const double* C = pose_buf(m, user_pose, a.pose_read);  // the candidate just evaluated
+    const double* S = lm_state(m, a.state_read);
+    if (lane < kNE) s_nc[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
+    if (lane < kLmWords) s_st[lane] = S[lane];
+    if (lane < 16) s_nc[kNE + lane] = C[lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    first = a.prev_first != 0;
+    accept = first || (s_nc[28] >= (double)a.min_valid && s_nc[27] / s_nc[28] <= s_st[16 + 27] / s_st[16 + 28]);
+    lam = s_st[45];
+    if (!first) lam = accept ? lam / 10.0 : fmax(lam * 10.0, 1e-4);
+    if (lane < kNE) s_ne[lane] = accept ? s_nc[lane] : s_st[16 + lane];
+    if (lane < 16) {
+      const double* Ta = accept ? s_nc + kNE : s_st;
+      tin[0] = Ta[ec];
+      tin[1] = Ta[4 + ec];
+      tin[2] = Ta[8 + ec];
+      tin[3] = Ta[lane];
+    }
   }
-  if (lane < kNE) s_ne[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  solve_update_wave(s_ne, a, tin, s_T, s_state);
+  if (final_only) {
+    if (lane < 16) s_T[lane] = tin[3];
+    if (lane == 0) *s_state = 0;
+  } else {
+    TrackArgs ta = a;
+    ta.lm_lambda = lam;
+    solve_update_wave(s_ne, ta, tin, s_T, s_state);
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -244,13 +299,20 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
     Tout[lane] = s_T[lane];
     if (state != 0 && a.pose_write != 2) pose_buf(m, user_pose, 1 - a.pose_write)[lane] = s_T[lane];
   }
+  if (LM && a.state_write >= 0) {
+    double* S = lm_state(m, a.state_write);
+    if (lane < 16) S[lane] = tin[3];
+    if (lane < kNE) S[16 + lane] = s_ne[lane];
+    if (lane == 0) S[45] = lam;
+  }
   if (lane == 0) {
     if (stats) {
       stats->cost = s_ne[27];
       stats->count = s_ne[28];
-      if (a.prev_first && a.prev_level >= 0 && a.prev_level < 8) stats->level_count[a.prev_level] = s_ne[28];
-      if (state == 0) stats->iters += 1;
-      else stats->flags |= (uint32_t)state;
+      if (a.prev_first && a.prev_level >= 0 && a.prev_level < 8)
+        stats->level_count[a.prev_level] = LM ? s_nc[28] : s_ne[28];
+      if (state != 0) stats->flags |= (uint32_t)state;
+      else if (LM ? (accept && !first) : !final_only) stats->iters += 1;
     }
     if (state != 0) {
       m.st->track_stop = 1;
@@ -259,11 +321,13 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
   }
 }
 
-template <int DF, int STORAGE>
+template <int DF, int STORAGE, bool LM>
 __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a) {
   __shared__ float s_t[kTerms][kTrackBlock + 1];
   __shared__ double s_g[kNE][kGroups + 1];
   __shared__ double s_ne[kNE];
+  __shared__ double s_nc[kLmWords];
+  __shared__ double s_st[kLmWords];
   __shared__ double s_T[16];
   __shared__ int s_state;
   const int jb = batch_job(b, blockIdx.x);
@@ -306,12 +370,18 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   }
   if (threadIdx.x < 64) {
     if (a.solve) {
-      solve_step(m, user_pose, a, stats, s_ne, s_T, &s_state, g0 == 0, stopped != 0);
+      solve_step<LM>(m, user_pose, a, stats, s_ne, s_T, &s_state, g0 == 0, stopped != 0, false, s_nc, s_st);
     } else {
       const double* Tin = pose_buf(m, user_pose, a.pose_read);
       if (threadIdx.x < 16) {
         s_T[threadIdx.x] = Tin[threadIdx.x];
         if (g0 == 0 && !stopped) pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
+      }
+      if (LM && g0 == 0 && !stopped && a.state_write >= 0) {
+        // the starting pose is the accepted one until the first decision
+        double* S = lm_state(m, a.state_write);
+        if (threadIdx.x < 16) S[threadIdx.x] = Tin[threadIdx.x];
+        if (threadIdx.x == 0) S[45] = a.lm_lambda;
       }
       if (threadIdx.x == 0) s_state = 0;
     }
@@ -399,6 +469,8 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
 // one workgroup per job.
 __global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a, double* out29) {
   __shared__ double s_ne[kNE];
+  __shared__ double s_nc[kLmWords];
+  __shared__ double s_st[kLmWords];
   __shared__ double s_T[16];
   __shared__ int s_state;
   const Job& J = b.job[blockIdx.x];
@@ -413,7 +485,8 @@ __global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a
     if (threadIdx.x < 16) user_pose[threadIdx.x] = pose_buf(m, user_pose, a.pose_read)[threadIdx.x];
     return;
   }
-  solve_step(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true, false);
+  if (a.adaptive) solve_step<true>(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true, false, true, s_nc, s_st);
+  else solve_step<false>(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true, false, false, s_nc, s_st);
 }
 
 __global__ void track_reset_kernel(Batch b) {
@@ -449,12 +522,23 @@ static void track_dispatch(Batch& b, int df, int st, const TrackArgs& a, hipStre
     total += track_tiles(b.job[j].f, a.level);
   }
   b.base[b.n] = total;
-  if (df == RF_DEPTH_U16) {
-    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<total, kTrackBlock, 0, s>>>(b, a);
-    else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<total, kTrackBlock, 0, s>>>(b, a);
+  const dim3 g(total), blk(kTrackBlock);
+  if (a.adaptive) {
+    if (df == RF_DEPTH_U16) {
+      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32, true><<<g, blk, 0, s>>>(b, a);
+      else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8, true><<<g, blk, 0, s>>>(b, a);
+    } else {
+      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32, true><<<g, blk, 0, s>>>(b, a);
+      else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8, true><<<g, blk, 0, s>>>(b, a);
+    }
   } else {
-    if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<total, kTrackBlock, 0, s>>>(b, a);
-    else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<total, kTrackBlock, 0, s>>>(b, a);
+    if (df == RF_DEPTH_U16) {
+      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32, false><<<g, blk, 0, s>>>(b, a);
+      else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8, false><<<g, blk, 0, s>>>(b, a);
+    } else {
+      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32, false><<<g, blk, 0, s>>>(b, a);
+      else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8, false><<<g, blk, 0, s>>>(b, a);
+    }
   }
 }
 
@@ -477,6 +561,9 @@ void launch_track(Batch& b, int df, int st, const rf_track_params& tp, hipStream
       a.pose_read = j > 0 ? (j - 1) % 2 : 2;
       a.pose_write = j % 2;
       a.mode = 0;
+      a.adaptive = tp.adaptive;
+      a.state_read = j > 0 ? (j - 1) % 2 : -1;
+      a.state_write = j % 2;
       track_dispatch(b, df, st, a, s);
       prev_level = l;
       prev_first = it == 0;
@@ -494,6 +581,9 @@ void launch_track(Batch& b, int df, int st, const rf_track_params& tp, hipStream
   a.acc_clear = -1;
   a.pose_read = (j - 1) % 2;
   a.pose_write = 2;
+  a.adaptive = tp.adaptive;
+  a.state_read = (j - 1) % 2;
+  a.state_write = -1;
   track_finalize_kernel<<<b.n, 64, 0, s>>>(b, a, nullptr);
 }
 

@@ -170,6 +170,29 @@ def test_track_pose_matches_fp64_oracle(rf, room):
         assert iters == room.levels * room.iters and fl == 0
 
 
+@pytest.mark.parametrize("lam0", [1e-4, 0.0])
+def test_track_lm_pose_matches_fp64_oracle(rf, room, lam0):
+    """Levenberg-Marquardt schedule (accept / reject on the mean cost): the GPU
+    decisions are taken on fixed-point totals, the oracle's on FP64 sums, so a
+    near-tie may be decided differently; the poses still agree to the bar."""
+    m, o64, o32 = integrate_teacher_forced(rf, room, range(2))
+    tp = rf.TrackParams(room.levels, room.iters, lm_lambda=lam0, adaptive=True)
+    for k in (2, 3):
+        T0 = room.poses[1]
+        P = dev_pose(T0)
+        stats = torch.zeros(16, dtype=torch.float64, device="cuda")
+        m.track(gpu_frame(rf, room, k), P, tp, None, stats)
+        T_ref, flags, st, trace = o64.track_lm(orc_frame(room, k), T0, room.levels, room.iters, lambda0=lam0)
+        assert flags == 0
+        dt, dr = pose_error(P.cpu().numpy(), T_ref)
+        assert dt <= 1e-4 and dr <= 1e-5, (k, dt, dr)
+        iters, fl = track_stats(stats)
+        assert fl == 0 and 0 < iters <= room.levels * (room.iters - 1)
+        assert abs(iters - int(st[2])) <= 2
+        gt_t, _ = pose_error(P.cpu().numpy(), room.poses[k])
+        assert gt_t < 5e-3
+
+
 def test_free_running_parity_room_poses(rf, room):
     """10 frames free-running: GPU pipeline vs FP64 oracle pipeline."""
     tp = rf.TrackParams(room.levels, room.iters)
