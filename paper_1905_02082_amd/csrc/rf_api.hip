@@ -35,7 +35,7 @@ rf_status check_launch(const char* what) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, dirty, total;
+  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, total;
   uint32_t dirty_cap;
 };
 
@@ -67,6 +67,7 @@ Layout layout_of(const rf_map_params* p) {
   L.rgb = o; o = align256(o + (size_t)p->max_blocks * 512 * 4);
   L.partials = o; o = align256(o + (size_t)rf::kTrackScratchWords * 8);
   L.md = o; o = align256(o + (size_t)p->max_pixels);
+  L.counts = o; o = align256(o + (size_t)rf::kIntegGroups * 8);
   L.dirty_cap = p->max_pixels / 16 + 64;
   L.dirty = o; o = align256(o + (size_t)L.dirty_cap * 2 * 4);  // two flag buffers
   L.total = o;
@@ -203,6 +204,7 @@ rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void
   d.rgb = reinterpret_cast<uchar4*>(a + L.rgb);
   d.partials = reinterpret_cast<double*>(a + L.partials);
   d.md = reinterpret_cast<uint8_t*>(a + L.md);
+  d.integ_counts = reinterpret_cast<uint2*>(a + L.counts);
   d.dirty = reinterpret_cast<uint32_t*>(a + L.dirty);
   d.max_pixels = p->max_pixels;
   d.dirty_cap = L.dirty_cap;

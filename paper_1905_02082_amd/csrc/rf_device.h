@@ -39,6 +39,7 @@ constexpr int kTrackBlock = RF_TRACK_BLOCK;  // 256: 16x16 pixel tile; 512: 32x1
 constexpr int kAccCopies = RF_ACC_COPIES;    // copies of the tracking accumulators
 // 3 accumulator buffers + 2 poses + 2 Levenberg-Marquardt states (48 words each)
 constexpr int kTrackScratchWords = 3 * kAccCopies * 29 * 16 + 32 + 2 * 48;
+constexpr int kIntegGroups = 1536;  // integration workgroups per launch (all jobs together)
 constexpr int kNE = 29;                    // 21 H + 6 g + cost + count
 constexpr int kTile = 32;                  // flood-fill tile edge
 
@@ -77,6 +78,7 @@ struct MapDev {
   DevState* st;
   double* partials;
   uint8_t* md;
+  uint2* integ_counts;  // per integration workgroup: (band, free) updates of the last integration
   uint32_t* dirty;
   uint32_t max_pixels;
   uint32_t dirty_cap;

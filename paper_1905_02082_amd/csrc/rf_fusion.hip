@@ -205,8 +205,6 @@ __global__ void reset_frame_list_kernel(Batch b) {
   if (threadIdx.x == 0 && (int)blockIdx.x < b.n) {
     DevState* st = b.job[blockIdx.x].m.st;
     st->f_count = 0;
-    st->n_band = 0;
-    st->n_free = 0;
   }
 }
 
@@ -326,26 +324,49 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       m.rgb[vidx[v]] = make_uchar4((unsigned char)ch[0], (unsigned char)ch[1], (unsigned char)ch[2], 0);
     }
   }
-  // per-workgroup update counts (band / free) for the roofline accounting
+  // per-workgroup update counts (band / free) for the roofline accounting:
+  // each workgroup writes its own slot (one atomic per workgroup on a shared
+  // counter would serialise ~1500 atomics per address), integ_fold_kernel sums
   __shared__ uint32_t s_cnt[2];
   if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
   __syncthreads();
   if (nb) atomicAdd(&s_cnt[0], nb);
   if (nf) atomicAdd(&s_cnt[1], nf);
   __syncthreads();
+  if (threadIdx.x == 0) m.integ_counts[g0] = make_uint2(s_cnt[0], s_cnt[1]);
+}
+
+// One workgroup per job: the integration's per-workgroup counts into the
+// map's counters (last integration and cumulative).
+__global__ __launch_bounds__(256) void integ_fold_kernel(Batch b) {
+  const Job& J = b.job[blockIdx.x];
+  const MapDev& m = J.m;
+  const int ng = b.base[blockIdx.x + 1] - b.base[blockIdx.x];
+  unsigned long long band = 0, free = 0;
+  for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    const uint2 c = m.integ_counts[i];
+    band += c.x;
+    free += c.y;
+  }
+  __shared__ unsigned long long s_b[256], s_f[256];
+  s_b[threadIdx.x] = band;
+  s_f[threadIdx.x] = free;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s_b[threadIdx.x] += s_b[threadIdx.x + w];
+      s_f[threadIdx.x] += s_f[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    if (s_cnt[0]) {
-      atomicAdd(&m.st->n_band, (unsigned long long)s_cnt[0]);
-      atomicAdd(&m.st->cum_band, (unsigned long long)s_cnt[0]);
-    }
-    if (s_cnt[1]) {
-      atomicAdd(&m.st->n_free, (unsigned long long)s_cnt[1]);
-      atomicAdd(&m.st->cum_free, (unsigned long long)s_cnt[1]);
-    }
-    if (g0 == 0) {
-      atomicAdd(&m.st->cum_blocks, (unsigned long long)nF);
-      atomicAdd(&m.st->cum_frames, 1ull);
-    }
+    DevState* st = m.st;
+    st->n_band = s_b[0];
+    st->n_free = s_f[0];
+    st->cum_band += s_b[0];
+    st->cum_free += s_f[0];
+    st->cum_blocks += min(st->f_count, m.flist_cap);
+    st->cum_frames += 1;
   }
 }
 
@@ -371,7 +392,7 @@ void launch_allocate(Batch& b, int depth_format, hipStream_t s) {
 void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
   // a fixed share of workgroups per job (block counts live on the device):
   // together one resident round (6 workgroups of 256 threads per CU)
-  const int per = 1536 / b.n;
+  const int per = kIntegGroups / b.n;
   for (int j = 0; j <= b.n; ++j) b.base[j] = j * per;
   const int grid = b.n * per;
   if (depth_format == RF_DEPTH_U16) {
@@ -381,6 +402,7 @@ void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
     if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<grid, 256, 0, s>>>(b);
     else integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(b);
   }
+  integ_fold_kernel<<<b.n, 256, 0, s>>>(b);
 }
 
 }  // namespace rf
