@@ -65,15 +65,22 @@ struct Dda {
     }
     left = n + 1;
   }
+  // Branch-free step: the axis with the smallest next-boundary parameter
+  // among those not yet at the end cell, ties to x, then y (the same choice
+  // as scanning x, y, z and keeping the first strict minimum).
   __device__ __forceinline__ void advance() {
-    int best = -1;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (c[a] == e[a]) continue;
-      if (best < 0 || tmax[a] < tmax[best]) best = a;
-    }
-    c[best] += step[best];
-    tmax[best] += tdel[best];
+    const float bx = (c[0] != e[0]) ? tmax[0] : INFINITY;
+    const float by = (c[1] != e[1]) ? tmax[1] : INFINITY;
+    const float bz = (c[2] != e[2]) ? tmax[2] : INFINITY;
+    const bool px = bx <= by && bx <= bz;
+    const bool py = !px && by <= bz;
+    const bool pz = !px && !py;
+    c[0] += px ? step[0] : 0;
+    c[1] += py ? step[1] : 0;
+    c[2] += pz ? step[2] : 0;
+    tmax[0] = px ? tmax[0] + tdel[0] : tmax[0];
+    tmax[1] = py ? tmax[1] + tdel[1] : tmax[1];
+    tmax[2] = pz ? tmax[2] + tdel[2] : tmax[2];
   }
 };
 
