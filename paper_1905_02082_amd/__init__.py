@@ -21,7 +21,7 @@ from ._native import (RF_DEPTH_F32, RF_DEPTH_U16, RF_FLAG_HASH_FULL, RF_FLAG_MAS
                       RF_STORAGE_FP16_U8, RF_STORAGE_FP32)
 
 __all__ = ["MapParams", "TrackParams", "MaskParams", "Frame", "Map", "Session", "Pipeline", "process_batch",
-           "RefusionError", "hashmap_bytes", "lib"]
+           "GraphStep", "RefusionError", "hashmap_bytes", "lib"]
 
 
 class RefusionError(RuntimeError):
@@ -126,6 +126,7 @@ class Frame:
         H, W = depth.shape
         _dev(rgb, "rgb", torch.uint8, (H, W, 3))
         self.depth, self.rgb = depth, rgb
+        self.fx, self.fy, self.cx, self.cy, self.depth_scale = fx, fy, cx, cy, depth_scale
         self.W, self.H = int(W), int(H)
         self.s = N.RfFrame(fx, fy, cx, cy, self.W, self.H, depth.data_ptr(), fmt,
                            depth_scale if fmt == N.RF_DEPTH_U16 else 1.0, rgb.data_ptr())
@@ -322,6 +323,55 @@ def _jobs(sessions, frames, mask=False, mask_out=False, stats=False):
     return arr
 
 
+def _stages(sessions, frames, tp: TrackParams, mp: MaskParams, dynamic, stream):
+    """The five stages of one step (the paper's Fig. 2 order) as callables that
+    enqueue their launch sets on `stream`:
+
+        registration without mask -> dynamic mask -> registration with mask
+        -> block allocation -> integration
+
+    A session whose first frame this is (k == 0) is only allocated and
+    integrated at its initial pose."""
+    if len(sessions) != len(frames):
+        raise RefusionError("one frame per session")
+    L = N.load()
+    st = _stream(stream)
+    run = [i for i, s in enumerate(sessions) if s.k > 0]
+    rs = [sessions[i] for i in run]
+    rf_ = [frames[i] for i in run]
+    tpc, mpc = tp.c(), mp.c()
+
+    def track1():
+        if rs:
+            _check(L.track_frame_batch(_jobs(rs, rf_, stats=True), len(rs), ctypes.byref(tpc), st),
+                   "track_frame_batch")
+
+    def mask():
+        if rs and dynamic:
+            _check(L.compute_dynamic_mask_batch(_jobs(rs, rf_, mask_out=True), len(rs), ctypes.byref(mpc), st),
+                   "compute_dynamic_mask_batch")
+
+    def track2():
+        if rs and dynamic:
+            _check(L.track_frame_batch(_jobs(rs, rf_, mask=True, stats=True), len(rs), ctypes.byref(tpc), st),
+                   "track_frame_batch")
+
+    def allocate_jobs():
+        jobs = _jobs(sessions, frames)
+        for i, s in enumerate(sessions):
+            use = dynamic and s.k > 0 and s.mask is not None
+            jobs[i].d_mask = s.mask.data_ptr() if use else None
+        return jobs
+
+    def allocate():
+        _check(L.hashmap_allocate_batch(allocate_jobs(), len(sessions), st), "hashmap_allocate_batch")
+
+    def integrate():
+        _check(L.integrate_frame_batch(allocate_jobs(), len(sessions), st), "integrate_frame_batch")
+
+    return [track1, mask, track2, allocate, integrate]
+
+
 def process_batch(sessions, frames, tp: TrackParams, mp: MaskParams, dynamic=True, stream=None, events=None):
     """One step of the method for several sessions at once (one frame each),
     one launch set per stage (the paper's Fig. 2 order):
@@ -333,58 +383,99 @@ def process_batch(sessions, frames, tp: TrackParams, mp: MaskParams, dynamic=Tru
     pose.  Every result is the same as processing the session alone.
     events: optional 6 torch.cuda.Event recorded on the stream before, between
     and after the five stages (for timing)."""
-    if len(sessions) != len(frames):
-        raise RefusionError("one frame per session")
-    L = N.load()
-    st = _stream(stream)
     tstream = stream if stream is not None else torch.cuda.current_stream()
-
-    def mark(i):
+    fns = _stages(sessions, frames, tp, mp, dynamic, tstream)
+    if events is not None:
+        events[0].record(tstream)
+    for i, fn in enumerate(fns):
+        fn()
         if events is not None:
-            events[i].record(tstream)
-
-    run = [i for i, s in enumerate(sessions) if s.k > 0]
-    mark(0)
-    if run:
-        rs = [sessions[i] for i in run]
-        rf_ = [frames[i] for i in run]
-        tpc = tp.c()
-        _check(L.track_frame_batch(_jobs(rs, rf_, stats=True), len(rs), ctypes.byref(tpc), st), "track_frame_batch")
-        mark(1)
-        if dynamic:
-            mpc = mp.c()
-            _check(L.compute_dynamic_mask_batch(_jobs(rs, rf_, mask_out=True), len(rs), ctypes.byref(mpc), st),
-                   "compute_dynamic_mask_batch")
-            mark(2)
-            _check(L.track_frame_batch(_jobs(rs, rf_, mask=True, stats=True), len(rs), ctypes.byref(tpc), st),
-                   "track_frame_batch")
-        else:
-            mark(2)
-    else:
-        mark(1)
-        mark(2)
-    mark(3)
-    use_mask = [dynamic and s.k > 0 for s in sessions]
-    jobs = _jobs(sessions, frames)
-    for i, s in enumerate(sessions):
-        jobs[i].d_mask = s.mask.data_ptr() if (use_mask[i] and s.mask is not None) else None
-    _check(L.hashmap_allocate_batch(jobs, len(sessions), st), "hashmap_allocate_batch")
-    mark(4)
-    _check(L.integrate_frame_batch(jobs, len(sessions), st), "integrate_frame_batch")
-    mark(5)
+            events[i + 1].record(tstream)
     for s in sessions:
         s.k += 1
 
 
+class GraphStep:
+    """process_batch recorded once as HIP graphs and replayed per step.
+
+    A frame costs about seventy launches, most of them the short tracking
+    iterations, so replaying a recorded graph removes most of the per-launch
+    submission cost.  Kernel arguments (the frame's buffers among them) are
+    fixed when recording, so the graphs read staging frames that this object
+    owns; each call copies the step's frames into them on the stream first.
+    The epoch that stamps allocated blocks advances on the device, so every
+    replay does exactly what an eager step does (the GPU tests check each
+    replay against eager steps bit for bit).
+
+    Record after every session's first frame; frames must keep the staging
+    frames' size, depth format and intrinsics.  split=True records one graph
+    per stage so that events can be placed between the stages."""
+
+    def __init__(self, sessions, frames_like, tp: TrackParams, mp: MaskParams, dynamic=True, split=False):
+        if any(s.k == 0 for s in sessions):
+            raise RefusionError("record a graph step after each session's first frame")
+        if len(sessions) != len(frames_like):
+            raise RefusionError("one frame per session")
+        self.sessions = list(sessions)
+        self.split = split
+        self.staging = [Frame(torch.empty_like(f.depth), torch.empty_like(f.rgb), f.fx, f.fy, f.cx, f.cy,
+                              f.depth_scale) for f in frames_like]
+        for s, f in zip(self.sessions, self.staging):
+            s._mask_for(f)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        fns = _stages(self.sessions, self.staging, tp, mp, dynamic, side)
+        groups = [[fn] for fn in fns] if split else [fns]
+        self.graphs = []
+        for grp in groups:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                for fn in grp:
+                    fn()
+            self.graphs.append(g)
+        torch.cuda.synchronize()
+
+    def __call__(self, frames, stream=None, events=None):
+        """Runs one step on `frames` (one per session).  events: optional 6
+        torch.cuda.Event; with split=False only the first and last are recorded.
+        The staging copies run between the first two."""
+        if len(frames) != len(self.staging):
+            raise RefusionError("one frame per session")
+        for f, g in zip(frames, self.staging):
+            if (f.depth.shape != g.depth.shape or f.depth.dtype != g.depth.dtype or f.s.fx != g.s.fx
+                    or f.s.fy != g.s.fy or f.s.cx != g.s.cx or f.s.cy != g.s.cy
+                    or f.s.depth_scale != g.s.depth_scale):
+                raise RefusionError("frame does not match the recorded staging frame")
+        stream = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(stream):
+            if events is not None:
+                events[0].record(stream)
+            for f, g in zip(frames, self.staging):
+                g.depth.copy_(f.depth, non_blocking=True)
+                g.rgb.copy_(f.rgb, non_blocking=True)
+            for i, gr in enumerate(self.graphs):
+                gr.replay()
+                if events is not None and self.split:
+                    events[i + 1].record(stream)
+            if events is not None and not self.split:
+                events[5].record(stream)
+        for s in self.sessions:
+            s.k += 1
+
+
 class Pipeline:
     """The per-frame method on one map with device-resident pose and mask
-    (process_batch with a single session)."""
+    (process_batch with a single session).  graph=True replays the steady-state
+    step as a recorded HIP graph (GraphStep), recorded at the second frame."""
 
     def __init__(self, params: MapParams, tp: TrackParams, mp: MaskParams, initial_pose, dynamic=True,
-                 device="cuda"):
+                 device="cuda", graph=False):
         self.session = Session(params, initial_pose, device)
         self.tp, self.mp = tp, mp
         self.dynamic = dynamic
+        self.graph = graph
+        self._step = None
 
     @property
     def map(self):
@@ -403,5 +494,10 @@ class Pipeline:
         return self.session.stats
 
     def process(self, frame: Frame, stream=None):
-        process_batch([self.session], [frame], self.tp, self.mp, self.dynamic, stream)
+        if self.graph and self.session.k > 0:
+            if self._step is None:
+                self._step = GraphStep([self.session], [frame], self.tp, self.mp, self.dynamic)
+            self._step([frame], stream)
+        else:
+            process_batch([self.session], [frame], self.tp, self.mp, self.dynamic, stream)
         return self.session.pose

@@ -190,7 +190,6 @@ rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void
   h.p = *p;
   h.arena = arena;
   h.bytes = bytes;
-  h.frame_id = 0;
   rf::MapDev& d = h.dev;
   d.st = reinterpret_cast<rf::DevState*>(a + L.st);
   d.buckets = reinterpret_cast<rf::Bucket*>(a + L.buckets);
@@ -233,7 +232,6 @@ rf_status hashmap_destroy(rf_map* m) {
 
 rf_status hashmap_reset(rf_map* m, void* stream) {
   if (!m) return fail(RF_EINVAL, "map is NULL");
-  m->h.frame_id = 0;
   rf::launch_map_init(m->h.dev, m->h.p.num_buckets, m->h.p.storage, S(stream));
   return check_launch("hashmap_reset");
 }
@@ -320,10 +318,6 @@ rf_status compute_dynamic_mask(rf_map* m, const rf_frame* f, const double* d_pos
 // ---------------------------------------------------------------- batched entry points
 rf_status hashmap_allocate_batch(const rf_job* jobs, int32_t n, void* stream) {
   auto fill = [&](const rf_job& j, rf::Job& J) -> rf_status {
-    rf::HostMap& h = j.map->h;
-    // frame stamps: 0 is the initial bucket value, so the epoch skips 0 on wrap
-    h.frame_id = (h.frame_id == 0xFFFFFFFFu) ? 1u : h.frame_id + 1u;
-    J.frame_id = h.frame_id;
     J.pose = j.d_pose;
     J.mask = j.d_mask;
     return RF_OK;

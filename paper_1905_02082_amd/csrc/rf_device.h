@@ -56,7 +56,8 @@ struct DevState {
   uint32_t track_counter;  // finished workgroups of the running tracking launch
   uint32_t track_stop;     // 1: the running registration pass stopped (degenerate)
   uint32_t dirty_count;    // flood fill: tiles marked since the last sweep
-  uint32_t pad[2];
+  uint32_t epoch;          // allocation epoch (frame stamps in the buckets), advanced on the device
+  uint32_t pad;
   unsigned long long n_band;  // voxels updated in the band by the last integration
   unsigned long long n_free;  // voxels carved by the last integration
   unsigned long long cum_band;    // since create/reset: band updates

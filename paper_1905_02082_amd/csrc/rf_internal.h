@@ -30,7 +30,6 @@ struct Job {
   uint8_t* eroded;
   uint8_t* filled;
   float* residual;
-  uint32_t frame_id;        // allocation epoch
   int tiles_x, tiles_y;     // flood-fill tile grid
   int band_groups;          // allocation: workgroups of band rays
   int carve_w, carve_h;     // allocation: carve-grid size
@@ -58,7 +57,6 @@ struct HostMap {
   void* arena;
   size_t bytes;
   MapDev dev;
-  uint32_t frame_id;  // allocation epoch (frame stamps in the buckets)
 };
 
 // Launchers: b holds 1..kMaxBatch jobs sharing depth format and storage.

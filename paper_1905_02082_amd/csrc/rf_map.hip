@@ -29,6 +29,7 @@ __global__ void init_state_kernel(DevState* st) {
     st->track_counter = 0;
     st->track_stop = 0;
     st->dirty_count = 0;
+    st->epoch = 0;
     st->n_band = 0;
     st->n_free = 0;
     st->cum_band = 0;
