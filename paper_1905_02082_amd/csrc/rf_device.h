@@ -33,7 +33,7 @@ constexpr float kMaxVoxelCoord = 8.0e6f;   // |voxel coordinate| limit (8 x 2^20
 #define RF_TRACK_BLOCK 256
 #endif
 #ifndef RF_ACC_COPIES
-#define RF_ACC_COPIES 16
+#define RF_ACC_COPIES 8
 #endif
 constexpr int kTrackBlock = RF_TRACK_BLOCK;  // 256: 16x16 pixel tile; 512: 32x16
 constexpr int kAccCopies = RF_ACC_COPIES;    // copies of the tracking accumulators

@@ -145,15 +145,17 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
   for (int c = 0; c < 6; ++c)
     if (c == r) row[c] *= (1.0 + a.lm_lambda);
   row[6] = -s_ne[21 + r];
+  double inv[6];  // reciprocal pivots, reused by the back substitution
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const double piv = readlane_f64(row[k], k);
     if (!(piv > 1e-12 * tr) && state == 0) state = RF_FLAG_TRACK_SINGULAR;
+    inv[k] = 1.0 / piv;
     double pk[7];
 #pragma unroll
     for (int c = k + 1; c < 7; ++c) pk[c] = readlane_f64(row[c], k);
     if (lane > k && lane < 6 && state == 0) {
-      const double fct = row[k] / piv;
+      const double fct = row[k] * inv[k];
 #pragma unroll
       for (int c = k + 1; c < 7; ++c) row[c] = fma(-fct, pk[c], row[c]);
     }
@@ -165,7 +167,7 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
       double s = readlane_f64(row[6], k);
 #pragma unroll
       for (int j = k + 1; j < 6; ++j) s = fma(-readlane_f64(row[j], k), x[j], s);
-      x[k] = s / readlane_f64(row[k], k);
+      x[k] = s * inv[k];
     }
   }
   if (lane < 16) {
@@ -179,11 +181,15 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
       const double p0 = x[3], p1 = x[4], p2 = x[5];
       const double th2 = p0 * p0 + p1 * p1 + p2 * p2;
       double A, B, C;
-      if (th2 < 1e-4) {
-        const double t4 = th2 * th2, t6 = t4 * th2;
-        A = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t6 * (1.0 / 5040.0);
-        B = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t6 * (1.0 / 40320.0);
-        C = (1.0 / 6.0) - th2 * (1.0 / 120.0) + t4 * (1.0 / 5040.0) - t6 * (1.0 / 362880.0);
+      if (th2 < 1e-2) {
+        // Taylor series of sin(th)/th, (1 - cos th)/th^2, (th - sin th)/th^3 in
+        // th^2 (Horner); for th < 0.1 the first omitted term is below 1e-18
+        A = fma(th2, fma(th2, fma(th2, fma(th2, fma(th2, -1.0 / 39916800.0, 1.0 / 362880.0), -1.0 / 5040.0),
+                                  1.0 / 120.0), -1.0 / 6.0), 1.0);
+        B = fma(th2, fma(th2, fma(th2, fma(th2, fma(th2, -1.0 / 479001600.0, 1.0 / 3628800.0), -1.0 / 40320.0),
+                                  1.0 / 720.0), -1.0 / 24.0), 0.5);
+        C = fma(th2, fma(th2, fma(th2, fma(th2, fma(th2, -1.0 / 6227020800.0, 1.0 / 39916800.0), -1.0 / 362880.0),
+                                  1.0 / 5040.0), -1.0 / 120.0), 1.0 / 6.0);
       } else {
         const double th = sqrt(th2), sn = sin(th), hs = sin(0.5 * th);
         A = sn / th;
@@ -244,9 +250,14 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
   double lam = a.lm_lambda;
   bool accept = true, first = true;
   if (!LM) {
-    // the pose goes through LDS (fewer registers held across the solve)
-    if (lane < 16) s_nc[kNE + lane] = pose_buf(m, user_pose, a.pose_read)[lane];
-    if (lane < kNE) s_ne[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
+    // pose and totals are loaded without branches (clamped lanes) so all the
+    // loads share one round trip; the pose goes through LDS (fewer registers
+    // held across the solve)
+    double pin = pose_buf(m, user_pose, a.pose_read)[lane < 16 ? lane : 0];
+    const double tot = fixed_total(acc_buf(m, a.acc_read) + (lane < kNE ? lane : 0) * kTermWords);
+    asm volatile("" : "+v"(pin));
+    if (lane < 16) s_nc[kNE + lane] = pin;
+    if (lane < kNE) s_ne[lane] = tot;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -259,9 +270,13 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
   } else {
     const double* C = pose_buf(m, user_pose, a.pose_read);  // the candidate just evaluated
     const double* S = lm_state(m, a.state_read);
-    if (lane < kNE) s_nc[lane] = fixed_total(acc_buf(m, a.acc_read) + lane * kTermWords);
-    if (lane < kLmWords) s_st[lane] = S[lane];
-    if (lane < 16) s_nc[kNE + lane] = C[lane];
+    double cin = C[lane < 16 ? lane : 0];
+    double st_in = S[lane < kLmWords ? lane : 0];
+    const double tot = fixed_total(acc_buf(m, a.acc_read) + (lane < kNE ? lane : 0) * kTermWords);
+    asm volatile("" : "+v"(cin), "+v"(st_in));
+    if (lane < kNE) s_nc[lane] = tot;
+    if (lane < kLmWords) s_st[lane] = st_in;
+    if (lane < 16) s_nc[kNE + lane] = cin;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -428,6 +443,10 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   __syncthreads();
 
   // thread (k, g) sums term k over pixels g, g + kGroups, ... in a fixed order
+  // as a depth and a photometric product chain.  Every term has the same
+  // shape (the count is the sum of 1 x 1 with a zero photometric weight), so
+  // the wavefronts do not diverge, and the loop is unrolled so its LDS reads
+  // are issued ahead of the FMAs.
   const double wc = (double)a.w_c;
   if (threadIdx.x < kNE * kGroups) {
     const int k = threadIdx.x % kNE, g = threadIdx.x / kNE;
@@ -442,19 +461,18 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     } else if (k < 27) {
       r = k - 21;
     }
-    // depth and photometric products in two independent chains
-    const int rd = (k < 21) ? r : (k < 27 ? r : 12), cd = (k < 21) ? c : 12;
-    const int rc = (k < 27) ? 6 + rd : 13, cc = (k < 21) ? 6 + c : 13;
+    // k < 21: H(r, c); k < 27: g(r); 27: cost; 28: count
+    const int rd = (k < 27) ? r : (k == 27 ? 12 : 14), cd = (k < 21) ? c : (k < 28 ? 12 : 14);
+    const int rc = (k < 27) ? 6 + r : (k == 27 ? 13 : 14), cc = (k < 21) ? 6 + c : (k < 28 ? 13 : 14);
+    const double wk = (k < 28) ? wc : 0.0;
     double acc_d = 0.0, acc_c = 0.0;
-    if (k < 28) {
-      for (int p = g; p < kTrackBlock; p += kGroups) {
-        acc_d = fma((double)s_t[rd][p], (double)s_t[cd][p], acc_d);
-        acc_c = fma((double)s_t[rc][p], (double)s_t[cc][p], acc_c);
-      }
-    } else {
-      for (int p = g; p < kTrackBlock; p += kGroups) acc_d += (double)s_t[14][p];
+#pragma unroll
+    for (int i = 0; i < kTrackBlock / kGroups; ++i) {
+      const int p = g + i * kGroups;
+      acc_d = fma((double)s_t[rd][p], (double)s_t[cd][p], acc_d);
+      acc_c = fma((double)s_t[rc][p], (double)s_t[cc][p], acc_c);
     }
-    s_g[k][g] = acc_d + wc * acc_c;
+    s_g[k][g] = acc_d + wk * acc_c;
   }
   __syncthreads();
   if (threadIdx.x < kNE) {
