@@ -121,7 +121,10 @@ typedef struct rf_map rf_map; /* opaque host handle */
  * spatial hash (linear probing, insert-only, as the paper never frees blocks).
  * ---------------------------------------------------------------------- */
 
-/* Bytes of device memory a map with these parameters needs. */
+/* Bytes of device memory a map with these parameters needs: the hash table,
+ * the voxel pool and its colours, and scratch for tracking (accumulators and
+ * a per-level, per-tile block cache of about 4 KiB per 256 pixels of
+ * max_pixels), the dynamic mask and integration. */
 rf_status hashmap_bytes(const rf_map_params* p, size_t* bytes);
 
 /* Creates a map inside the caller's device arena (>= hashmap_bytes bytes,

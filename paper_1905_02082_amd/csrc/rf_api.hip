@@ -35,8 +35,8 @@ rf_status check_launch(const char* what) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, total;
-  uint32_t dirty_cap;
+  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, total;
+  uint32_t dirty_cap, tc_tiles;
 };
 
 bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
@@ -70,6 +70,10 @@ Layout layout_of(const rf_map_params* p) {
   L.counts = o; o = align256(o + (size_t)rf::kIntegGroups * 8);
   L.dirty_cap = p->max_pixels / 16 + 64;
   L.dirty = o; o = align256(o + (size_t)L.dirty_cap * 2 * 4);  // two flag buffers
+  // tracking block cache: the 16x16 tiles of a max_pixels frame plus slack
+  // for ragged edges; tiles beyond it use the hash table alone
+  L.tc_tiles = (p->max_pixels + 255) / 256 + 64;
+  L.tcache = o; o = align256(o + (size_t)rf::kCacheLevels * L.tc_tiles * rf::kTileRefs * sizeof(rf::BlockRef));
   L.total = o;
   return L;
 }
@@ -205,6 +209,8 @@ rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void
   d.md = reinterpret_cast<uint8_t*>(a + L.md);
   d.integ_counts = reinterpret_cast<uint2*>(a + L.counts);
   d.dirty = reinterpret_cast<uint32_t*>(a + L.dirty);
+  d.tcache = reinterpret_cast<rf::BlockRef*>(a + L.tcache);
+  d.tc_tiles = L.tc_tiles;
   d.max_pixels = p->max_pixels;
   d.dirty_cap = L.dirty_cap;
   d.s = p->voxel_size;

@@ -9,6 +9,7 @@
 //   rgb          max_blocks x 512 x  uchar4 (RGB + pad)
 //   partials     tracking: 3 buffers of 29 fixed-point accumulators (128 B apart) + 2 poses
 //   mask scratch max_pixels bytes + two buffers of per-tile dirty flags for the flood fill
+//   tile refs    tracking block cache: kCacheLevels x tc_tiles x kTileRefs x 16 B {key, slot, epoch}
 //
 // Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
 // linear probing, insertion by 64-bit CAS on the key word (insert-only: keys
@@ -43,6 +44,23 @@ constexpr int kIntegGroups = 1536;  // integration workgroups per launch (all jo
 constexpr int kNE = 29;                    // 21 H + 6 g + cost + count
 constexpr int kTile = 32;                  // flood-fill tile edge
 
+// Tracking block cache: for every pyramid level below kCacheLevels and every
+// tracking tile, the (block key, pool slot) pairs its pixels looked up in the
+// last launch at that level.  A pair of an existing block stays valid for
+// good (blocks are never moved or removed; a reset or a new map clears the
+// cache); an absent block is kept with slot -1 and the allocation epoch in
+// which it was absent, and is valid only while that epoch lasts.
+struct alignas(16) BlockRef {
+  unsigned long long key;
+  int slot;
+  uint32_t epoch;
+};
+constexpr int kCacheLevels = 4;  // pyramid levels with a block cache
+constexpr int kTileRefs = 128;   // pair capacity per tile (level l keeps at most tile_refs(l))
+// A 16x16 tile of level l covers 4^l times the area of a level-0 tile, so it
+// touches more blocks: 32 pairs at level 0, 64 at level 1, 128 from level 2.
+__host__ __device__ constexpr int tile_refs(int level) { return level >= 2 ? 128 : 32 << level; }
+
 struct alignas(16) Bucket {
   unsigned long long key;
   uint32_t slot;
@@ -66,6 +84,13 @@ struct DevState {
   unsigned long long cum_frames;  // since create/reset: integrations
 };
 
+// Starts a new allocation epoch: 0 is the stamp of a bucket never touched,
+// so the epoch skips it on wrap.
+__device__ __forceinline__ void advance_epoch(DevState* st) {
+  const uint32_t e = st->epoch;
+  st->epoch = (e == 0xFFFFFFFFu) ? 1u : e + 1u;
+}
+
 struct MapDev {
   Bucket* buckets;
   uint32_t bucket_mask;
@@ -80,6 +105,8 @@ struct MapDev {
   double* partials;
   uint8_t* md;
   uint2* integ_counts;  // per integration workgroup: (band, free) updates of the last integration
+  BlockRef* tcache;     // tracking block cache (kCacheLevels x tc_tiles tiles of kTileRefs pairs)
+  uint32_t tc_tiles;    // tiles per level with a cache entry (later tiles look up the hash table only)
   uint32_t* dirty;
   uint32_t max_pixels;
   uint32_t dirty_cap;
@@ -261,13 +288,51 @@ __device__ __forceinline__ void trilinear(const float c[8], const float f[3], fl
   }
 }
 
+// Pool slots of the distinct corner blocks of a trilinear lookup, from the
+// hash table.  Corner k = dx + 2 dy + 4 dz lies in block (b0 + d) & cross; the
+// distinct blocks are the corners k with k & ~cross == 0, and sl[k] of the
+// others is copied from sl[k & cross].  The first probes are issued together
+// (one round trip), and only collisions probe further.  Only the loaded key
+// and slot stay live across the round trip; the key and home bucket are
+// recomputed afterwards (cheaper than registers).  False if a block is absent.
+struct HashSlots {
+  __device__ __forceinline__ bool operator()(const MapDev& m, int bx0, int by0, int bz0, int cross, int sl[8]) const {
+    unsigned long long bkey[8];
+    uint32_t bslot[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if ((k & ~cross) != 0) continue;
+      const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
+      const Bucket* p = m.buckets + (hash3(x, y, z) & m.bucket_mask);
+      bkey[k] = p->key;
+      bslot[k] = p->slot;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if ((k & ~cross) != 0) {
+        sl[k] = sl[k & cross];
+        continue;
+      }
+      const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
+      Bucket b0;
+      b0.key = bkey[k];
+      b0.slot = bslot[k];
+      sl[k] = resolve_slot(m, b0, pack_key(x, y, z), hash3(x, y, z) & m.bucket_mask);
+      if (sl[k] < 0) return false;
+    }
+    return true;
+  }
+};
+
 // Trilinear sample of the TSDF (and, with WANT_COLOUR, of the model intensity)
 // at world point y.  Defined only if all 8 corner voxels lie in allocated
 // blocks and have weight > 0.  Gradients are with respect to world
 // coordinates (d/dg * 1/s).
-template <int STORAGE, bool WANT_GRAD, bool WANT_COLOUR>
+// `slots` finds the pool slots of the corner blocks (HashSlots: the hash
+// table; tracking adds a per-tile cache in front of it).
+template <int STORAGE, bool WANT_GRAD, bool WANT_COLOUR, class Slots = HashSlots>
 __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], float& S, float gS[3],
-                                           float& Iv, float gI[3]) {
+                                           float& Iv, float gI[3], const Slots& slots = Slots()) {
   float fr[3];
   int i0[3];
 #pragma unroll
@@ -280,35 +345,8 @@ __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], fl
   }
   const int bx0 = i0[0] >> 3, by0 = i0[1] >> 3, bz0 = i0[2] >> 3;
   const int cross = ((i0[0] & 7) == 7 ? 1 : 0) | ((i0[1] & 7) == 7 ? 2 : 0) | ((i0[2] & 7) == 7 ? 4 : 0);
-  // Corner k = dx + 2 dy + 4 dz lies in block (b0 + d) & cross; the distinct
-  // blocks are the corners k with k & ~cross == 0.  Their first probes are
-  // issued together (one round trip), and only collisions probe further.
-  // Only the loaded key and slot stay live across the round trip; the key
-  // and home bucket are recomputed afterwards (cheaper than registers).
-  unsigned long long bkey[8];
-  uint32_t bslot[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if ((k & ~cross) != 0) continue;
-    const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
-    const Bucket* p = m.buckets + (hash3(x, y, z) & m.bucket_mask);
-    bkey[k] = p->key;
-    bslot[k] = p->slot;
-  }
   int sl[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if ((k & ~cross) != 0) {
-      sl[k] = sl[k & cross];
-      continue;
-    }
-    const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
-    Bucket b0;
-    b0.key = bkey[k];
-    b0.slot = bslot[k];
-    sl[k] = resolve_slot(m, b0, pack_key(x, y, z), hash3(x, y, z) & m.bucket_mask);
-    if (sl[k] < 0) return false;
-  }
+  if (!slots(m, bx0, by0, bz0, cross, sl)) return false;
   // All corner records (and colours) are loaded before any weight is
   // tested, so the loads share one round trip instead of one each.  The
   // empty asm statements pin every loaded value to this point: without them

@@ -209,15 +209,13 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
 }
 
 // Starts an allocation: empties the frame list and advances the epoch that
-// stamps the buckets this frame touches.  0 is the stamp of a bucket never
-// touched, so the epoch skips it on wrap.  The epoch lives on the device, so a
+// stamps the buckets this frame touches.  The epoch lives on the device, so a
 // recorded launch sequence (a HIP graph of a frame) replays correctly.
 __global__ void reset_frame_list_kernel(Batch b) {
   if (threadIdx.x == 0 && (int)blockIdx.x < b.n) {
     DevState* st = b.job[blockIdx.x].m.st;
     st->f_count = 0;
-    const uint32_t e = st->epoch;
-    st->epoch = (e == 0xFFFFFFFFu) ? 1u : e + 1u;
+    advance_epoch(st);
   }
 }
 

@@ -39,8 +39,20 @@ __global__ void init_state_kernel(DevState* st) {
   }
 }
 
+__global__ void init_refs_kernel(BlockRef* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = BlockRef{kEmptyKey, -1, 0u};
+}
+
+// Imported blocks end the allocation epoch, so no tracking cache keeps an
+// absent-block entry across an import.
+__global__ void advance_epoch_kernel(DevState* st) {
+  if (threadIdx.x == 0) advance_epoch(st);
+}
+
 void launch_map_init(const MapDev& m, uint32_t num_buckets, int storage, hipStream_t s) {
   init_state_kernel<<<1, 64, 0, s>>>(m.st);
+  init_refs_kernel<<<256, 256, 0, s>>>(m.tcache, (size_t)kCacheLevels * m.tc_tiles * kTileRefs);
   init_buckets_kernel<<<2048, 256, 0, s>>>(m.buckets, num_buckets);
   const size_t rec = (storage == RF_STORAGE_FP32) ? 8 : 4;
   zero_words_kernel<<<4096, 256, 0, s>>>(reinterpret_cast<uint4*>(m.sdfw), (size_t)m.max_blocks * 512 * rec / 16);
@@ -185,6 +197,7 @@ void launch_import(const MapDev& m, int storage, const int32_t* keys, const floa
                    const uint8_t* rgb, uint32_t n, hipStream_t s) {
   if (n == 0) return;
   const int grid = (int)(n < 4096 ? n : 4096);
+  advance_epoch_kernel<<<1, 64, 0, s>>>(m.st);
   if (storage == RF_STORAGE_FP32) import_kernel<RF_STORAGE_FP32><<<grid, 256, 0, s>>>(m, keys, sdf, w, rgb, n);
   else import_kernel<RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(m, keys, sdf, w, rgb, n);
 }

@@ -336,6 +336,99 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
   }
 }
 
+// Per-workgroup block cache in LDS (open addressing, linear probing):
+// built from the tile's cached pairs before the first barrier, consulted
+// before the hash table, extended with every pair the hash table resolves,
+// and written back (the pairs used in this launch) for the next launch at
+// this level and tile.  A slot still being written reads as kNoSlot, which a
+// lookup treats as a miss, so concurrent inserts never yield a wrong slot.
+constexpr int kHashSlots = 2 * kTileRefs;
+constexpr int kNoSlot = (int)0x80000000;
+constexpr int kMaxProbe = 16;  // a key is placed within 16 slots of its home or not cached
+
+struct TileCache {
+  unsigned long long* key;  // kHashSlots, kEmptyKey when free
+  int* slot;                // kHashSlots, kNoSlot until written
+  uint32_t* used;           // kHashSlots, 1 when looked up in this launch
+
+  __device__ __forceinline__ void insert(int x, int y, int z, unsigned long long k, int sl, bool mark) const {
+    uint32_t h = hash3(x, y, z) & (kHashSlots - 1);
+#pragma unroll 1
+    for (int i = 0; i < kMaxProbe; ++i) {
+      const unsigned long long old = atomicCAS(&key[h], kEmptyKey, k);
+      if (old == kEmptyKey) {
+        slot[h] = sl;
+        if (mark) used[h] = 1u;
+        return;
+      }
+      if (old == k) {
+        if (mark) used[h] = 1u;
+        return;
+      }
+      h = (h + 1) & (kHashSlots - 1);
+    }
+  }
+
+  __device__ __forceinline__ int find(int x, int y, int z, unsigned long long k) const {
+    uint32_t h = hash3(x, y, z) & (kHashSlots - 1);
+#pragma unroll 1
+    for (int i = 0; i < kMaxProbe; ++i) {
+      const unsigned long long kk = key[h];
+      if (kk == k) {
+        const int sl = slot[h];
+        if (sl != kNoSlot) used[h] = 1u;
+        return sl;
+      }
+      if (kk == kEmptyKey) break;
+      h = (h + 1) & (kHashSlots - 1);
+    }
+    return kNoSlot;
+  }
+};
+
+// Slot resolution of sample_map through the tile cache: cached blocks cost
+// an LDS probe; the others take the hash table (first probes of all missing
+// corner blocks issued together) and are added to the cache.
+struct CachedSlots {
+  TileCache c;
+  __device__ __forceinline__ bool operator()(const MapDev& m, int bx0, int by0, int bz0, int cross, int sl[8]) const {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if ((k & ~cross) != 0) continue;
+      const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
+      sl[k] = c.find(x, y, z, pack_key(x, y, z));
+    }
+    unsigned long long bkey[8];
+    uint32_t bslot[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if ((k & ~cross) != 0 || sl[k] != kNoSlot) continue;
+      const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
+      const Bucket* p = m.buckets + (hash3(x, y, z) & m.bucket_mask);
+      bkey[k] = p->key;
+      bslot[k] = p->slot;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if ((k & ~cross) != 0 || sl[k] != kNoSlot) continue;
+      const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
+      Bucket b0;
+      b0.key = bkey[k];
+      b0.slot = bslot[k];
+      const unsigned long long key = pack_key(x, y, z);
+      sl[k] = resolve_slot(m, b0, key, hash3(x, y, z) & m.bucket_mask);
+      c.insert(x, y, z, key, sl[k], true);
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if ((k & ~cross) != 0) sl[k] = sl[k & cross];
+      ok &= sl[k] >= 0;
+    }
+    return ok;
+  }
+};
+
 template <int DF, int STORAGE, bool LM>
 __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a) {
   __shared__ float s_t[kTerms][kTrackBlock + 1];
@@ -345,6 +438,10 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   __shared__ double s_st[kLmWords];
   __shared__ double s_T[16];
   __shared__ int s_state;
+  __shared__ unsigned long long s_hk[kHashSlots];
+  __shared__ int s_hs[kHashSlots];
+  __shared__ uint32_t s_used[kHashSlots];
+  __shared__ uint32_t s_nref;
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const MapDev& m = J.m;
@@ -356,6 +453,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   // Set only by earlier launches.  Read here but acted on after the pixel
   // loads and the solve are under way: only publishing waits for it.
   const uint32_t stopped = m.st->track_stop;
+  const uint32_t epoch = m.st->epoch;
 
   // pose-independent loads first, so their latency overlaps the solve
   // workgroup = kTileW x 16 tile of the level's pixel grid, wavefront = 8x8 sub-tile
@@ -382,6 +480,37 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     const int per = (kUsedWords + ng - 1) / ng;
     const int q1 = min(g0 * per + per, kUsedWords);
     for (int q = g0 * per + threadIdx.x; q < q1; q += kTrackBlock) *used_word(acc_buf(m, a.acc_clear), q) = 0ull;
+  }
+  // the tile's cached block pairs (wavefront 1, while wavefront 0 solves);
+  // tiles without a cache entry start from an empty table
+  const bool cached = a.level < kCacheLevels && g0 < (int)m.tc_tiles;
+  BlockRef* tab = m.tcache + ((size_t)(cached ? a.level : 0) * m.tc_tiles + (cached ? g0 : 0)) * kTileRefs;
+  const TileCache cache{s_hk, s_hs, s_used};
+  const int nrefs = tile_refs(a.level);
+  if (wave == 1) {
+    const BlockRef none{kEmptyKey, -1, 0u};
+    const BlockRef e0 = (cached && lane < nrefs) ? tab[lane] : none;
+    const BlockRef e1 = (cached && lane + 64 < nrefs) ? tab[lane + 64] : none;
+#pragma unroll
+    for (int q = 0; q < kHashSlots / 64; ++q) {
+      s_hk[lane + 64 * q] = kEmptyKey;
+      s_hs[lane + 64 * q] = kNoSlot;
+      s_used[lane + 64 * q] = 0u;
+    }
+    if (lane == 0) s_nref = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (e0.key != kEmptyKey && (e0.slot >= 0 || e0.epoch == epoch)) {
+      int x, y, z;
+      unpack_key(e0.key, x, y, z);
+      cache.insert(x, y, z, e0.key, e0.slot, false);
+    }
+    if (e1.key != kEmptyKey && (e1.slot >= 0 || e1.epoch == epoch)) {
+      int x, y, z;
+      unpack_key(e1.key, x, y, z);
+      cache.insert(x, y, z, e1.key, e1.slot, false);
+    }
   }
   if (threadIdx.x < 64) {
     if (a.solve) {
@@ -420,7 +549,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     float y[3];
     xform(R, t, x, y);
     float S, gS[3], Iv, gI[3];
-    if (sample_map<STORAGE, true, true>(m, y, S, gS, Iv, gI) && fabsf(S) < m.tau) {
+    if (sample_map<STORAGE, true, true>(m, y, S, gS, Iv, gI, CachedSlots{cache}) && fabsf(S) < m.tau) {
       term[0] = gS[0];
       term[1] = gS[1];
       term[2] = gS[2];
@@ -441,6 +570,17 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
 #pragma unroll
   for (int k = 0; k < kTerms; ++k) s_t[k][threadIdx.x] = term[k];
   __syncthreads();
+  // the pairs used in this launch become the tile's cache for the next one
+  if (cached) {
+    for (int h = threadIdx.x; h < kHashSlots; h += kTrackBlock) {
+      const unsigned long long kk = s_hk[h];
+      const int ss = s_hs[h];
+      if (kk != kEmptyKey && ss != kNoSlot && s_used[h]) {
+        const uint32_t pos = atomicAdd(&s_nref, 1u);
+        if (pos < (uint32_t)nrefs) tab[pos] = BlockRef{kk, ss, epoch};
+      }
+    }
+  }
 
   // thread (k, g) sums term k over pixels g, g + kGroups, ... in a fixed order
   // as a depth and a photometric product chain.  Every term has the same
@@ -475,6 +615,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     s_g[k][g] = acc_d + wk * acc_c;
   }
   __syncthreads();
+  if (cached && threadIdx.x < nrefs && threadIdx.x >= s_nref) tab[threadIdx.x] = BlockRef{kEmptyKey, -1, 0u};
   if (threadIdx.x < kNE) {
     double tot = 0.0;
 #pragma unroll
