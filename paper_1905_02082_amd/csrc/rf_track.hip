@@ -336,20 +336,35 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
   }
 }
 
-// Per-workgroup block cache in LDS (open addressing, linear probing):
-// built from the tile's cached pairs before the first barrier, consulted
-// before the hash table, extended with every pair the hash table resolves,
-// and written back (the pairs used in this launch) for the next launch at
-// this level and tile.  A slot still being written reads as kNoSlot, which a
-// lookup treats as a miss, so concurrent inserts never yield a wrong slot.
+// Per-workgroup block cache in LDS: a direct-mapped window of kWin^3 blocks
+// centred on the bounding box of the tile's cached blocks (one indexed read,
+// no key to compare) and, for blocks outside it, a small open-addressing
+// hash (linear probing).  Built from the tile's cached pairs before the first
+// barrier, consulted before the hash table, extended with every pair the hash
+// table resolves, and written back (the pairs used in this launch) for the
+// next launch at this level and tile.  A slot still being written reads as
+// kNoSlot, which a lookup treats as a miss, so concurrent inserts never
+// yield a wrong slot.
 constexpr int kHashSlots = 2 * kTileRefs;
 constexpr int kNoSlot = (int)0x80000000;
 constexpr int kMaxProbe = 16;  // a key is placed within 16 slots of its home or not cached
+constexpr int kWin = 8;        // direct-mapped window of kWin^3 blocks around the tile's blocks
+constexpr int kWinCells = kWin * kWin * kWin;
+constexpr int kFarOrigin = 0x40000000;  // window origin that no block coordinate reaches
 
 struct TileCache {
   unsigned long long* key;  // kHashSlots, kEmptyKey when free
   int* slot;                // kHashSlots, kNoSlot until written
   uint32_t* used;           // kHashSlots, 1 when looked up in this launch
+  int* grid;                // kWin^3 window of block slots (kNoSlot: unknown)
+  uint8_t* gused;           // kWin^3, 1 when looked up in this launch
+  int ax, ay, az;           // window origin (block coordinates)
+
+  // window cell of block (x,y,z), or -1 outside the window
+  __device__ __forceinline__ int cell(int x, int y, int z) const {
+    const uint32_t dx = (uint32_t)(x - ax), dy = (uint32_t)(y - ay), dz = (uint32_t)(z - az);
+    return (dx < (uint32_t)kWin && dy < (uint32_t)kWin && dz < (uint32_t)kWin) ? (int)(dx + kWin * (dy + kWin * dz)) : -1;
+  }
 
   __device__ __forceinline__ void insert(int x, int y, int z, unsigned long long k, int sl, bool mark) const {
     uint32_t h = hash3(x, y, z) & (kHashSlots - 1);
@@ -392,11 +407,24 @@ struct TileCache {
 struct CachedSlots {
   TileCache c;
   __device__ __forceinline__ bool operator()(const MapDev& m, int bx0, int by0, int bz0, int cross, int sl[8]) const {
+    // window cells of all eight corner blocks read together (one LDS round trip)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int cl = c.cell(bx0 + (k & 1), by0 + ((k >> 1) & 1), bz0 + (k >> 2));
+      sl[k] = c.grid[cl >= 0 ? cl : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(sl[k]));
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if ((k & ~cross) != 0) continue;
       const int x = bx0 + (k & 1), y = by0 + ((k >> 1) & 1), z = bz0 + (k >> 2);
-      sl[k] = c.find(x, y, z, pack_key(x, y, z));
+      const int cl = c.cell(x, y, z);
+      if (cl >= 0) {
+        if (sl[k] != kNoSlot) c.gused[cl] = 1;
+      } else {
+        sl[k] = c.find(x, y, z, pack_key(x, y, z));
+      }
     }
     unsigned long long bkey[8];
     uint32_t bslot[8];
@@ -417,7 +445,13 @@ struct CachedSlots {
       b0.slot = bslot[k];
       const unsigned long long key = pack_key(x, y, z);
       sl[k] = resolve_slot(m, b0, key, hash3(x, y, z) & m.bucket_mask);
-      c.insert(x, y, z, key, sl[k], true);
+      const int cl = c.cell(x, y, z);
+      if (cl >= 0) {
+        c.grid[cl] = sl[k];
+        c.gused[cl] = 1;
+      } else {
+        c.insert(x, y, z, key, sl[k], true);
+      }
     }
     bool ok = true;
 #pragma unroll
@@ -441,6 +475,9 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   __shared__ unsigned long long s_hk[kHashSlots];
   __shared__ int s_hs[kHashSlots];
   __shared__ uint32_t s_used[kHashSlots];
+  __shared__ int s_grid[kWinCells];
+  __shared__ uint8_t s_gused[kWinCells];
+  __shared__ int s_org[3];
   __shared__ uint32_t s_nref;
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
@@ -485,7 +522,6 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   // tiles without a cache entry start from an empty table
   const bool cached = a.level < kCacheLevels && g0 < (int)m.tc_tiles;
   BlockRef* tab = m.tcache + ((size_t)(cached ? a.level : 0) * m.tc_tiles + (cached ? g0 : 0)) * kTileRefs;
-  const TileCache cache{s_hk, s_hs, s_used};
   const int nrefs = tile_refs(a.level);
   if (wave == 1) {
     const BlockRef none{kEmptyKey, -1, 0u};
@@ -497,19 +533,53 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
       s_hs[lane + 64 * q] = kNoSlot;
       s_used[lane + 64 * q] = 0u;
     }
+#pragma unroll
+    for (int q = 0; q < kWinCells / 64; ++q) {
+      s_grid[lane + 64 * q] = kNoSlot;
+      s_gused[lane + 64 * q] = 0;
+    }
     if (lane == 0) s_nref = 0u;
+    // window origin: centre of the bounding box of the valid cached blocks
+    const bool v0 = e0.key != kEmptyKey && (e0.slot >= 0 || e0.epoch == epoch);
+    const bool v1 = e1.key != kEmptyKey && (e1.slot >= 0 || e1.epoch == epoch);
+    int p0[3], p1[3], lo[3], hi[3];
+    unpack_key(v0 ? e0.key : 0ull, p0[0], p0[1], p0[2]);
+    unpack_key(v1 ? e1.key : 0ull, p1[0], p1[1], p1[2]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = min(v0 ? p0[q] : INT_MAX, v1 ? p1[q] : INT_MAX);
+      hi[q] = max(v0 ? p0[q] : INT_MIN, v1 ? p1[q] : INT_MIN);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = min(lo[q], __shfl_xor(lo[q], o));
+        hi[q] = max(hi[q], __shfl_xor(hi[q], o));
+      }
+    }
+    const bool any = lo[0] <= hi[0];
+    int org[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) org[q] = any ? ((lo[q] + hi[q]) >> 1) - (kWin / 2 - 1) : kFarOrigin;
+    if (lane == 0) {
+      s_org[0] = org[0];
+      s_org[1] = org[1];
+      s_org[2] = org[2];
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (e0.key != kEmptyKey && (e0.slot >= 0 || e0.epoch == epoch)) {
-      int x, y, z;
-      unpack_key(e0.key, x, y, z);
-      cache.insert(x, y, z, e0.key, e0.slot, false);
+    const TileCache wc{s_hk, s_hs, s_used, s_grid, s_gused, org[0], org[1], org[2]};
+    if (v0) {
+      const int cl = wc.cell(p0[0], p0[1], p0[2]);
+      if (cl >= 0) s_grid[cl] = e0.slot;
+      else wc.insert(p0[0], p0[1], p0[2], e0.key, e0.slot, false);
     }
-    if (e1.key != kEmptyKey && (e1.slot >= 0 || e1.epoch == epoch)) {
-      int x, y, z;
-      unpack_key(e1.key, x, y, z);
-      cache.insert(x, y, z, e1.key, e1.slot, false);
+    if (v1) {
+      const int cl = wc.cell(p1[0], p1[1], p1[2]);
+      if (cl >= 0) s_grid[cl] = e1.slot;
+      else wc.insert(p1[0], p1[1], p1[2], e1.key, e1.slot, false);
     }
   }
   if (threadIdx.x < 64) {
@@ -532,6 +602,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   }
   __syncthreads();
   if (stopped || s_state != 0) return;  // stopped or degenerate: pose kept, the pass stops
+  const TileCache cache{s_hk, s_hs, s_used, s_grid, s_gused, s_org[0], s_org[1], s_org[2]};
 
   float term[kTerms];
 #pragma unroll
@@ -572,6 +643,14 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   __syncthreads();
   // the pairs used in this launch become the tile's cache for the next one
   if (cached) {
+    for (int h = threadIdx.x; h < kWinCells; h += kTrackBlock) {
+      const int ss = s_grid[h];
+      if (ss != kNoSlot && s_gused[h]) {
+        const uint32_t pos = atomicAdd(&s_nref, 1u);
+        const unsigned long long kk = pack_key(cache.ax + h % kWin, cache.ay + (h / kWin) % kWin, cache.az + h / (kWin * kWin));
+        if (pos < (uint32_t)nrefs) tab[pos] = BlockRef{kk, ss, epoch};
+      }
+    }
     for (int h = threadIdx.x; h < kHashSlots; h += kTrackBlock) {
       const unsigned long long kk = s_hk[h];
       const int ss = s_hs[h];
