@@ -36,6 +36,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <type_traits>
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -170,8 +171,11 @@ inline bool depth_valid(float D, float dmax) { return D > 0.0f && D <= dmax; }
 
 template <class Real>
 inline Real luminance(const uint8_t* c) {
-  // ((0.2126 R + 0.7152 G) + 0.0722 B) / 255
-  return ((Real)0.2126f*(Real)c[0] + (Real)0.7152f*(Real)c[1] + (Real)0.0722f*(Real)c[2]) / (Real)255.0f;
+  // ((0.2126 R + 0.7152 G) + 0.0722 B) / 255; the FP32 mirror scales by the
+  // FP32 reciprocal of 255, as the kernels do, the reference divides exactly
+  const Real x = (Real)0.2126f*(Real)c[0] + (Real)0.7152f*(Real)c[1] + (Real)0.0722f*(Real)c[2];
+  if (std::is_same<Real, float>::value) return x * (Real)(1.0f / 255.0f);
+  return x / (Real)255.0f;
 }
 
 // --------------------------------------------------------------------------

@@ -243,8 +243,10 @@ __device__ __forceinline__ float load_depth(const FrameDev& f, int idx) {
 __device__ __forceinline__ bool depth_ok(float D, float dmax) { return D > 0.0f && D <= dmax; }
 
 // ((0.2126 R + 0.7152 G) + 0.0722 B) / 255
+// Intensity in [0, 1] (Sec. III-B): the weighted sum scaled by the FP32
+// reciprocal of 255 (a multiplication instead of a correctly rounded division).
 __device__ __forceinline__ float luminance(float r, float g, float b) {
-  return ((0.2126f * r + 0.7152f * g) + 0.0722f * b) / 255.0f;
+  return ((0.2126f * r + 0.7152f * g) + 0.0722f * b) * (1.0f / 255.0f);
 }
 
 // Float copy of the FP64 pose: R row-major, t.
