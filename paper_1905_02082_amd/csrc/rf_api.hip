@@ -35,7 +35,7 @@ rf_status check_launch(const char* what) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, total;
+  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, total;
   uint32_t dirty_cap, tc_tiles;
 };
 
@@ -73,7 +73,8 @@ Layout layout_of(const rf_map_params* p) {
   // tracking block cache: the 16x16 tiles of a max_pixels frame plus slack
   // for ragged edges; tiles beyond it use the hash table alone
   L.tc_tiles = (p->max_pixels + 255) / 256 + 64;
-  L.tcache = o; o = align256(o + (size_t)rf::kCacheLevels * L.tc_tiles * rf::kTileRefs * sizeof(rf::BlockRef));
+  L.tcache = o; o = align256(o + (size_t)rf::tile_refs_before(rf::kCacheLevels) * L.tc_tiles * sizeof(rf::BlockRef));
+  L.tc_count = o; o = align256(o + (size_t)rf::kCacheLevels * L.tc_tiles * 4);
   L.total = o;
   return L;
 }
@@ -210,6 +211,7 @@ rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void
   d.integ_counts = reinterpret_cast<uint2*>(a + L.counts);
   d.dirty = reinterpret_cast<uint32_t*>(a + L.dirty);
   d.tcache = reinterpret_cast<rf::BlockRef*>(a + L.tcache);
+  d.tc_count = reinterpret_cast<uint32_t*>(a + L.tc_count);
   d.tc_tiles = L.tc_tiles;
   d.max_pixels = p->max_pixels;
   d.dirty_cap = L.dirty_cap;

@@ -9,7 +9,8 @@
 //   rgb          max_blocks x 512 x  uchar4 (RGB + pad)
 //   partials     tracking: 3 buffers of 29 fixed-point accumulators (128 B apart) + 2 poses
 //   mask scratch max_pixels bytes + two buffers of per-tile dirty flags for the flood fill
-//   tile refs    tracking block cache: kCacheLevels x tc_tiles x kTileRefs x 16 B {key, slot, epoch}
+//   tile refs    tracking block cache: per level l < kCacheLevels, tc_tiles x tile_refs(l) x 16 B {key, slot, epoch},
+//                then kCacheLevels x tc_tiles x 4 B pair counts
 //
 // Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
 // linear probing, insertion by 64-bit CAS on the key word (insert-only: keys
@@ -56,10 +57,15 @@ struct alignas(16) BlockRef {
   uint32_t epoch;
 };
 constexpr int kCacheLevels = 4;  // pyramid levels with a block cache
-constexpr int kTileRefs = 128;   // pair capacity per tile (level l keeps at most tile_refs(l))
+constexpr int kTileRefs = 256;   // largest pair capacity of a tile
 // A 16x16 tile of level l covers 4^l times the area of a level-0 tile, so it
-// touches more blocks: 32 pairs at level 0, 64 at level 1, 128 from level 2.
-__host__ __device__ constexpr int tile_refs(int level) { return level >= 2 ? 128 : 32 << level; }
+// touches more blocks: 64 pairs at level 0, 128 at level 1, 256 from level 2.
+__host__ __device__ constexpr int tile_refs(int level) { return level >= 2 ? 256 : 64 << level; }
+// First pair of level l's region, in units of tiles (region l holds
+// tc_tiles x tile_refs(l) pairs).
+__host__ __device__ constexpr int tile_refs_before(int level) {
+  return level <= 0 ? 0 : tile_refs(level - 1) + tile_refs_before(level - 1);
+}
 
 struct alignas(16) Bucket {
   unsigned long long key;
@@ -105,7 +111,8 @@ struct MapDev {
   double* partials;
   uint8_t* md;
   uint2* integ_counts;  // per integration workgroup: (band, free) updates of the last integration
-  BlockRef* tcache;     // tracking block cache (kCacheLevels x tc_tiles tiles of kTileRefs pairs)
+  BlockRef* tcache;     // tracking block cache (per level: tc_tiles tiles of tile_refs(level) pairs)
+  uint32_t* tc_count;   // valid pairs of each cached tile (kCacheLevels x tc_tiles)
   uint32_t tc_tiles;    // tiles per level with a cache entry (later tiles look up the hash table only)
   uint32_t* dirty;
   uint32_t max_pixels;

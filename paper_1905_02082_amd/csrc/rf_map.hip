@@ -52,7 +52,8 @@ __global__ void advance_epoch_kernel(DevState* st) {
 
 void launch_map_init(const MapDev& m, uint32_t num_buckets, int storage, hipStream_t s) {
   init_state_kernel<<<1, 64, 0, s>>>(m.st);
-  init_refs_kernel<<<256, 256, 0, s>>>(m.tcache, (size_t)kCacheLevels * m.tc_tiles * kTileRefs);
+  init_refs_kernel<<<256, 256, 0, s>>>(m.tcache, (size_t)tile_refs_before(kCacheLevels) * m.tc_tiles);
+  zero_words_kernel<<<16, 256, 0, s>>>(reinterpret_cast<uint4*>(m.tc_count), ((size_t)kCacheLevels * m.tc_tiles + 3) / 4);
   init_buckets_kernel<<<2048, 256, 0, s>>>(m.buckets, num_buckets);
   const size_t rec = (storage == RF_STORAGE_FP32) ? 8 : 4;
   zero_words_kernel<<<4096, 256, 0, s>>>(reinterpret_cast<uint4*>(m.sdfw), (size_t)m.max_blocks * 512 * rec / 16);

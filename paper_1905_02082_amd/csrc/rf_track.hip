@@ -345,9 +345,9 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
 // next launch at this level and tile.  A slot still being written reads as
 // kNoSlot, which a lookup treats as a miss, so concurrent inserts never
 // yield a wrong slot.
-constexpr int kHashSlots = 2 * kTileRefs;
+constexpr int kHashSlots = kTileRefs;
 constexpr int kNoSlot = (int)0x80000000;
-constexpr int kMaxProbe = 16;  // a key is placed within 16 slots of its home or not cached
+constexpr int kMaxProbe = 8;   // a key is placed within 8 slots of its home or not cached
 constexpr int kWin = 8;        // direct-mapped window of kWin^3 blocks around the tile's blocks
 constexpr int kWinCells = kWin * kWin * kWin;
 constexpr int kFarOrigin = 0x40000000;  // window origin that no block coordinate reaches
@@ -355,7 +355,7 @@ constexpr int kFarOrigin = 0x40000000;  // window origin that no block coordinat
 struct TileCache {
   unsigned long long* key;  // kHashSlots, kEmptyKey when free
   int* slot;                // kHashSlots, kNoSlot until written
-  uint32_t* used;           // kHashSlots, 1 when looked up in this launch
+  uint8_t* used;            // kHashSlots, 1 when looked up in this launch
   int* grid;                // kWin^3 window of block slots (kNoSlot: unknown)
   uint8_t* gused;           // kWin^3, 1 when looked up in this launch
   int ax, ay, az;           // window origin (block coordinates)
@@ -373,11 +373,11 @@ struct TileCache {
       const unsigned long long old = atomicCAS(&key[h], kEmptyKey, k);
       if (old == kEmptyKey) {
         slot[h] = sl;
-        if (mark) used[h] = 1u;
+        if (mark) used[h] = 1;
         return;
       }
       if (old == k) {
-        if (mark) used[h] = 1u;
+        if (mark) used[h] = 1;
         return;
       }
       h = (h + 1) & (kHashSlots - 1);
@@ -391,7 +391,7 @@ struct TileCache {
       const unsigned long long kk = key[h];
       if (kk == k) {
         const int sl = slot[h];
-        if (sl != kNoSlot) used[h] = 1u;
+        if (sl != kNoSlot) used[h] = 1;
         return sl;
       }
       if (kk == kEmptyKey) break;
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   __shared__ int s_state;
   __shared__ unsigned long long s_hk[kHashSlots];
   __shared__ int s_hs[kHashSlots];
-  __shared__ uint32_t s_used[kHashSlots];
+  __shared__ uint8_t s_used[kHashSlots];
   __shared__ int s_grid[kWinCells];
   __shared__ uint8_t s_gused[kWinCells];
   __shared__ int s_org[3];
@@ -521,17 +521,22 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   // the tile's cached block pairs (wavefront 1, while wavefront 0 solves);
   // tiles without a cache entry start from an empty table
   const bool cached = a.level < kCacheLevels && g0 < (int)m.tc_tiles;
-  BlockRef* tab = m.tcache + ((size_t)(cached ? a.level : 0) * m.tc_tiles + (cached ? g0 : 0)) * kTileRefs;
+  BlockRef* tab = m.tcache + (size_t)m.tc_tiles * tile_refs_before(cached ? a.level : 0) +
+                  (size_t)(cached ? g0 : 0) * tile_refs(cached ? a.level : 0);
+  uint32_t* tcount = m.tc_count + (size_t)(cached ? a.level : 0) * m.tc_tiles + (cached ? g0 : 0);
   const int nrefs = tile_refs(a.level);
   if (wave == 1) {
     const BlockRef none{kEmptyKey, -1, 0u};
-    const BlockRef e0 = (cached && lane < nrefs) ? tab[lane] : none;
-    const BlockRef e1 = (cached && lane + 64 < nrefs) ? tab[lane + 64] : none;
+    constexpr int kLoads = kTileRefs / 64;
+    const int cnt = cached ? (int)min(*tcount, (uint32_t)nrefs) : 0;
+    BlockRef e[kLoads];
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) e[q] = (cached && lane + 64 * q < nrefs) ? tab[lane + 64 * q] : none;
 #pragma unroll
     for (int q = 0; q < kHashSlots / 64; ++q) {
       s_hk[lane + 64 * q] = kEmptyKey;
       s_hs[lane + 64 * q] = kNoSlot;
-      s_used[lane + 64 * q] = 0u;
+      s_used[lane + 64 * q] = 0;
     }
 #pragma unroll
     for (int q = 0; q < kWinCells / 64; ++q) {
@@ -540,28 +545,31 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     }
     if (lane == 0) s_nref = 0u;
     // window origin: centre of the bounding box of the valid cached blocks
-    const bool v0 = e0.key != kEmptyKey && (e0.slot >= 0 || e0.epoch == epoch);
-    const bool v1 = e1.key != kEmptyKey && (e1.slot >= 0 || e1.epoch == epoch);
-    int p0[3], p1[3], lo[3], hi[3];
-    unpack_key(v0 ? e0.key : 0ull, p0[0], p0[1], p0[2]);
-    unpack_key(v1 ? e1.key : 0ull, p1[0], p1[1], p1[2]);
+    bool v[kLoads];
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      lo[q] = min(v0 ? p0[q] : INT_MAX, v1 ? p1[q] : INT_MAX);
-      hi[q] = max(v0 ? p0[q] : INT_MIN, v1 ? p1[q] : INT_MIN);
+    for (int q = 0; q < kLoads; ++q) {
+      v[q] = lane + 64 * q < cnt && e[q].key != kEmptyKey && (e[q].slot >= 0 || e[q].epoch == epoch);
+      int p[3];
+      unpack_key(e[q].key, p[0], p[1], p[2]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = min(lo[d], v[q] ? p[d] : INT_MAX);
+        hi[d] = max(hi[d], v[q] ? p[d] : INT_MIN);
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        lo[q] = min(lo[q], __shfl_xor(lo[q], o));
-        hi[q] = max(hi[q], __shfl_xor(hi[q], o));
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = min(lo[d], __shfl_xor(lo[d], o));
+        hi[d] = max(hi[d], __shfl_xor(hi[d], o));
       }
     }
     const bool any = lo[0] <= hi[0];
     int org[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) org[q] = any ? ((lo[q] + hi[q]) >> 1) - (kWin / 2 - 1) : kFarOrigin;
+    for (int d = 0; d < 3; ++d) org[d] = any ? ((lo[d] + hi[d]) >> 1) - (kWin / 2 - 1) : kFarOrigin;
     if (lane == 0) {
       s_org[0] = org[0];
       s_org[1] = org[1];
@@ -571,15 +579,14 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const TileCache wc{s_hk, s_hs, s_used, s_grid, s_gused, org[0], org[1], org[2]};
-    if (v0) {
-      const int cl = wc.cell(p0[0], p0[1], p0[2]);
-      if (cl >= 0) s_grid[cl] = e0.slot;
-      else wc.insert(p0[0], p0[1], p0[2], e0.key, e0.slot, false);
-    }
-    if (v1) {
-      const int cl = wc.cell(p1[0], p1[1], p1[2]);
-      if (cl >= 0) s_grid[cl] = e1.slot;
-      else wc.insert(p1[0], p1[1], p1[2], e1.key, e1.slot, false);
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) {
+      if (!v[q]) continue;
+      int p[3];
+      unpack_key(e[q].key, p[0], p[1], p[2]);
+      const int cl = wc.cell(p[0], p[1], p[2]);
+      if (cl >= 0) s_grid[cl] = e[q].slot;
+      else wc.insert(p[0], p[1], p[2], e[q].key, e[q].slot, false);
     }
   }
   if (threadIdx.x < 64) {
@@ -694,7 +701,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     s_g[k][g] = acc_d + wk * acc_c;
   }
   __syncthreads();
-  if (cached && threadIdx.x < nrefs && threadIdx.x >= s_nref) tab[threadIdx.x] = BlockRef{kEmptyKey, -1, 0u};
+  if (cached && threadIdx.x == 0) *tcount = min(s_nref, (uint32_t)nrefs);
   if (threadIdx.x < kNE) {
     double tot = 0.0;
 #pragma unroll
