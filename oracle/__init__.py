@@ -65,6 +65,7 @@ def _load():
         "orc_export": (c_int64, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64]),
         "orc_import": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64]),
         "orc_surface": (c_int64, [c_void_p, c_void_p, c_int64]),
+        "orc_mesh": (c_int64, [c_void_p, c_void_p, c_int64]),
         "orc_se3_exp": (None, [c_void_p, c_void_p]),
         "orc_pose_left_update": (None, [c_void_p, c_void_p]),
         "orc_solve6": (c_int, [c_void_p, c_double, c_void_p]),
@@ -215,6 +216,14 @@ class OracleMap:
         out = np.zeros((max(n, 1), 7), np.float64)
         if n:
             self.L.orc_surface(self.h, out.ctypes.data, n)
+        return out[:n]
+
+    def mesh(self):
+        """Marching-tetrahedra triangles (n,3,3): three vertices x, y, z each."""
+        n = self.L.orc_mesh(self.h, None, 0)
+        out = np.zeros((max(n, 1), 3, 3), np.float64)
+        if n:
+            self.L.orc_mesh(self.h, out.ctypes.data, n)
         return out[:n]
 
     def sample(self, y):

@@ -676,6 +676,108 @@ int64_t surface(const Map<Real>& m, double* out, int64_t cap) {
   return n;
 }
 
+// Triangle mesh of the zero level set (the model is shown as a mesh, Sec. I
+// and Fig. 1), by marching tetrahedra.  Reading: a cube of 8 voxel centres
+// (lower corner v, corner k = dx + 2 dy + 4 dz at v + (dx, dy, dz)) is meshed
+// when all 8 voxels exist, are observed (w > 0) and have |sdf| < tau (the
+// condition the zero-crossing extraction applies per edge).  The cube is cut
+// into the six tetrahedra along its diagonal 0-7, (0, a, a|b, 7) for the six
+// orders of the axis bits a, b, c; neighbouring cubes cut their shared faces
+// alike, so the mesh is closed wherever the cubes are.  Inside means
+// sdf < 0.  A tetrahedron with one vertex on its own side gives one triangle
+// (the crossings of that vertex's three edges), with two and two a quad (two
+// triangles).  A crossing on edge (a, b), a the corner whose bits are a
+// subset of b's, is P_a + t (P_b - P_a) with t = f_a / (f_a - f_b), per axis
+// in the order written, so the same grid edge gives the same point in every
+// tetrahedron and cube.  Triangles face the observed (positive) side: a
+// triangle whose normal (q1 - q0) x (q2 - q0) has a negative dot product with
+// (sum of outside vertices / their count - sum of inside vertices / their
+// count), scaled to (n_in * sum_out - n_out * sum_in), is reversed.
+// out: 9 values per triangle (3 vertices x, y, z); returns the count.
+template <class Real>
+int64_t mesh(const Map<Real>& m, double* out, int64_t cap) {
+  static const int kTets[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7},
+                                  {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+  std::vector<Key> keys;
+  for (auto& kv : m.blocks) keys.push_back(kv.first);
+  std::sort(keys.begin(), keys.end());
+  const Real s = (Real)m.P.voxel_size, tau = (Real)m.P.truncation;
+  int64_t n = 0;
+  auto emit = [&](const Real* q0, const Real* q1, const Real* q2) {
+    if (n < cap) {
+      double* o = out + 9*n;
+      for (int a = 0; a < 3; ++a) { o[a] = (double)q0[a]; o[3+a] = (double)q1[a]; o[6+a] = (double)q2[a]; }
+    }
+    ++n;
+  };
+  for (const Key& b : keys) {
+    for (int l = 0; l < 512; ++l) {
+      const int32_t v[3] = {8*b.x + (l & 7), 8*b.y + ((l >> 3) & 7), 8*b.z + (l >> 6)};
+      Real f[8], P[8][3];
+      bool ok = true;
+      for (int k = 0; k < 8 && ok; ++k) {
+        const int32_t c[3] = {v[0] + (k & 1), v[1] + ((k >> 1) & 1), v[2] + (k >> 2)};
+        const Voxel<Real>* vx = m.voxel(c[0], c[1], c[2]);
+        if (!vx || !(vx->w > 0) || !(std::fabs(vx->sdf) < tau)) { ok = false; break; }
+        f[k] = vx->sdf;
+        for (int a = 0; a < 3; ++a) P[k][a] = (Real)c[a] * s;
+      }
+      if (!ok) continue;
+      for (const auto& T : kTets) {
+        int ins[4], outs[4], ni = 0, no = 0;
+        for (int j = 0; j < 4; ++j) {
+          if (f[T[j]] < 0) ins[ni++] = T[j];
+          else outs[no++] = T[j];
+        }
+        if (ni == 0 || no == 0) continue;
+        // crossing point of the edge between corners i and o
+        auto cross = [&](int i, int o, Real* q) {
+          const int lo = (i & o) == i ? i : o, hi = lo == i ? o : i;  // lo's bits are a subset of hi's
+          const Real t = f[lo] / (f[lo] - f[hi]);
+          for (int a = 0; a < 3; ++a) q[a] = P[lo][a] + t * (P[hi][a] - P[lo][a]);
+        };
+        // orientation reference: n_in * sum(outside) - n_out * sum(inside)
+        Real ref[3];
+        for (int a = 0; a < 3; ++a) {
+          Real so = 0, si = 0;
+          for (int j = 0; j < no; ++j) so += P[outs[j]][a];
+          for (int j = 0; j < ni; ++j) si += P[ins[j]][a];
+          ref[a] = (Real)ni * so - (Real)no * si;
+        }
+        auto facing = [&](const Real* q0, const Real* q1, const Real* q2) {
+          const Real e1[3] = {q1[0] - q0[0], q1[1] - q0[1], q1[2] - q0[2]};
+          const Real e2[3] = {q2[0] - q0[0], q2[1] - q0[1], q2[2] - q0[2]};
+          const Real nx = e1[1]*e2[2] - e1[2]*e2[1], ny = e1[2]*e2[0] - e1[0]*e2[2], nz = e1[0]*e2[1] - e1[1]*e2[0];
+          return (nx*ref[0] + ny*ref[1]) + nz*ref[2] >= 0;
+        };
+        if (ni == 1 || no == 1) {
+          const int lone = ni == 1 ? ins[0] : outs[0];
+          const int* other = ni == 1 ? outs : ins;
+          Real q[3][3];
+          for (int j = 0; j < 3; ++j) cross(lone, other[j], q[j]);
+          if (facing(q[0], q[1], q[2])) emit(q[0], q[1], q[2]);
+          else emit(q[0], q[2], q[1]);
+        } else {
+          // quad: (i0,o0) (i0,o1) (i1,o1) (i1,o0) is a cycle of crossing edges
+          Real q[4][3];
+          cross(ins[0], outs[0], q[0]);
+          cross(ins[0], outs[1], q[1]);
+          cross(ins[1], outs[1], q[2]);
+          cross(ins[1], outs[0], q[3]);
+          if (facing(q[0], q[1], q[2])) {
+            emit(q[0], q[1], q[2]);
+            emit(q[0], q[2], q[3]);
+          } else {
+            emit(q[0], q[2], q[1]);
+            emit(q[0], q[3], q[2]);
+          }
+        }
+      }
+    }
+  }
+  return n;
+}
+
 template <class Real>
 Map<Real>* as(void* h) { return static_cast<Map<Real>*>(static_cast<MapBase*>(h)); }
 
@@ -909,6 +1011,13 @@ int64_t orc_surface(void* p, double* out, int64_t cap) {
   OrcMap* h = (OrcMap*)p;
   if (h->real_bits == 32) return surface(*as<float>(h->m), out, cap);
   return surface(*as<double>(h->m), out, cap);
+}
+
+// Mesh triangles: 9 doubles each.  Returns the count (writes at most cap).
+int64_t orc_mesh(void* p, double* out, int64_t cap) {
+  OrcMap* h = (OrcMap*)p;
+  if (h->real_bits == 32) return mesh(*as<float>(h->m), out, cap);
+  return mesh(*as<double>(h->m), out, cap);
 }
 
 // ---- single-operation entry points used by the pins ----------------------

@@ -154,6 +154,7 @@ class Sequence:
     iters: int
     carve_stride: int
     seed: int
+    prims: np.ndarray = None     # static primitives of the scene (records as rendered), for accuracy metrics
 
     @property
     def n(self):
@@ -330,7 +331,7 @@ def static_room(n_frames=300, seed=1905020822, width=640, height=480):
                                 seed, noise=True, dropout=0.02)
     return Sequence("static_room", width, height, fx, fy, cx, cy, poses, depth, rgb, labels, 0.001,
                     voxel_size=0.01, truncation=0.03, depth_max=5.0, num_buckets=1 << 20,
-                    levels=3, iters=10, carve_stride=4, seed=seed)
+                    levels=3, iters=10, carve_stride=4, seed=seed, prims=P)
 
 
 def dynamic_room(n_frames=400, seed=1905020823, width=640, height=480, n_clusters=None, movers="sweep"):

@@ -3,6 +3,8 @@
 * ``fill_map``: a voxel-block map (sorted int32 keys, sdf, weight, RGB8) whose
   voxel values are a given analytic field sampled at the voxel centres v*s.
 * ``ray_depth``: depth images of analytic planes/spheres from a pinhole camera.
+* ``scene_distance``: distance of points to the surface of a rendered scene's
+  static primitives (the ground truth of the synthetic model-accuracy metric).
 
 These are input generators only; they hold none of the mapping method's
 arithmetic (no interpolation, projection rules, averaging or tracking).
@@ -83,3 +85,30 @@ def ray_depth_sphere(pose, W, H, fx, fy, cx, cy, centre, radius, background=None
     if background is not None:
         t = np.minimum(t, background)
     return t
+
+
+def scene_distance(prims, points):
+    """Unsigned distance (float64) of each point to the nearest surface of the
+    primitives (records as synth renders them: room interior, boxes with yaw
+    about world z, spheres, capsules)."""
+    pts = np.asarray(points, np.float64).reshape(-1, 3)
+    best = np.full(len(pts), np.inf)
+    for r in np.asarray(prims, np.float64):
+        kind, c, h = int(r[0]), r[2:5], r[5:8]
+        d = pts - c
+        if kind in (0, 1):
+            co, si = (r[8], r[9]) if kind == 1 else (1.0, 0.0)
+            local = np.stack([co * d[:, 0] + si * d[:, 1], -si * d[:, 0] + co * d[:, 1], d[:, 2]], 1)
+            q = np.abs(local) - h
+            sd = np.linalg.norm(np.maximum(q, 0.0), axis=1) + np.minimum(q.max(axis=1), 0.0)
+            dist = np.abs(sd)
+        elif kind == 2:
+            dist = np.abs(np.linalg.norm(d, axis=1) - h[0])
+        else:
+            a = r[17:20]
+            p0 = c - a
+            ba = 2.0 * a
+            t = np.clip(((pts - p0) @ ba) / max(float(ba @ ba), 1e-300), 0.0, 1.0)
+            dist = np.abs(np.linalg.norm(pts - (p0 + t[:, None] * ba), axis=1) - h[0])
+        best = np.minimum(best, dist)
+    return best

@@ -642,3 +642,92 @@ def test_allocation_equals_union_of_segment_cells():
         outer_all |= outer
     assert inner_all <= F <= outer_all
     assert m.num_blocks == len(F)
+
+
+# ---------------------------------------------------------------- mesh (marching tetrahedra)
+
+def sphere_mesh(centre, r, s=0.01, tau=0.05, real_bits=64, hole=None):
+    """Oracle mesh of an exact sphere SDF (clamped to +-tau) sampled at the
+    voxel centres of every block near the sphere; hole: voxel index whose
+    weight is zeroed."""
+    ang = np.linspace(0, 2 * np.pi, 90)
+    pol = np.linspace(0, np.pi, 45)
+    pts = centre + r * np.array([[np.cos(a) * np.sin(b), np.sin(a) * np.sin(b), np.cos(b)] for a in ang for b in pol])
+    keys = A.blocks_near(pts, s, 1)
+    k, sdf, w, rgb = A.fill_map(keys, s, lambda x: np.clip(np.linalg.norm(x - centre, axis=-1) - r, -tau, tau))
+    if hole is not None:
+        v = np.asarray(hole)
+        b, l = v // 8, v % 8
+        i = np.nonzero((k == b).all(1))[0][0]
+        w[i, l[0] + 8 * l[1] + 64 * l[2]] = 0.0
+    om = O.OracleMap(s, tau, 5.0, 255, 4, real_bits=real_bits)
+    om.import_(k, sdf, w, rgb)
+    return om.mesh()
+
+
+def test_mesh_of_sphere_matches_closed_form():
+    c, r = np.array([0.013, -0.007, 0.021]), 0.2
+    T = sphere_mesh(c, r)
+    V = T.reshape(-1, 3)
+    # vertices: crossings of chords of length <= sqrt(3) s, so within (sqrt(3) s)^2 / (8 r) of the sphere
+    assert np.abs(np.linalg.norm(V - c, axis=1) - r).max() <= 3 * 0.01 ** 2 / (8 * r) * 1.01
+    area = 0.5 * np.linalg.norm(np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]), axis=1).sum()
+    vol = np.einsum("ij,ij->i", T[:, 0] - c, np.cross(T[:, 1] - c, T[:, 2] - c)).sum() / 6.0
+    assert abs(area / (4 * np.pi * r * r) - 1) < 2e-3
+    assert abs(vol / (4.0 / 3.0 * np.pi * r ** 3) - 1) < 2e-3   # positive: normals face outward
+
+
+def test_mesh_is_closed_and_consistently_oriented():
+    T = sphere_mesh(np.array([0.004, 0.011, -0.002]), 0.12)
+    V, idx = np.unique(T.reshape(-1, 3), axis=0, return_inverse=True)
+    F = idx.reshape(-1, 3)
+    assert (F[:, 0] != F[:, 1]).all() and (F[:, 1] != F[:, 2]).all() and (F[:, 0] != F[:, 2]).all()
+    directed = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+    d_set = set(map(tuple, directed))
+    assert len(d_set) == len(directed)                         # each directed edge once
+    assert all((b, a) in d_set for a, b in d_set)              # and its reverse once: closed, oriented
+    E = len(directed) // 2
+    assert len(V) - E + len(F) == 2                            # Euler characteristic of a sphere
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mesh_of_plane_lies_on_the_plane(seed):
+    rng = np.random.default_rng(seed)
+    n = rng.normal(size=3)
+    n /= np.linalg.norm(n)
+    d0 = rng.uniform(-0.02, 0.02)
+    s, tau = 0.01, 0.06
+    keys = np.array([[x, y, z] for x in range(-1, 1) for y in range(-1, 1) for z in range(-1, 1)], np.int32)
+    k, sdf, w, rgb = A.fill_map(keys, s, lambda x: np.clip(x @ n - d0, -tau, tau))
+    om = O.OracleMap(s, tau, 5.0, 255, 4, real_bits=64)
+    om.import_(k, sdf, w, rgb)
+    T = om.mesh()
+    assert len(T) > 100
+    assert np.abs(T.reshape(-1, 3) @ n - d0).max() < 1e-12      # a linear field is interpolated exactly
+    nrm = np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0])
+    big = np.linalg.norm(nrm, axis=1) > 1e-10
+    assert (nrm[big] @ n > 0).all()                            # facing the positive side
+
+
+def test_mesh_skips_cubes_with_an_unobserved_corner():
+    c, r = np.array([0.0, 0.0, 0.0]), 0.1
+    full = sphere_mesh(c, r)
+    v = np.array([10, 0, 0])                                   # a voxel on the sphere (x = 0.1 m)
+    holed = sphere_mesh(c, r, hole=v)
+    lo = v * 0.01 - 0.01 - 1e-9
+    hi = v * 0.01 + 0.01 + 1e-9
+    inside = lambda T: ((T >= lo) & (T <= hi)).all(axis=2).all(axis=1)
+    # the 8 cubes around the voxel lose all their triangles; nothing else changes
+    keep = ~inside(full)
+    assert inside(full).sum() > 0 and inside(holed).sum() == 0
+    a = np.sort(full[keep].reshape(len(full[keep]), -1), axis=0)
+    b = np.sort(holed.reshape(len(holed), -1), axis=0)
+    assert a.shape == b.shape and np.array_equal(a, b)
+
+
+def test_mesh_fp32_mirror_close_to_fp64():
+    c, r = np.array([0.013, -0.007, 0.021]), 0.15
+    T64 = sphere_mesh(c, r)
+    T32 = sphere_mesh(c, r, real_bits=32)
+    assert T64.shape == T32.shape                   # same cubes, same cases, same emission order
+    assert np.abs(T64 - T32).max() < 1e-6
