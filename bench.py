@@ -23,6 +23,7 @@ from device counters of voxel updates.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -90,6 +91,49 @@ def track_footprint(seq, block_keys, frame_ids, storage):
             out[lv] += voxel_ids.size * rec + ub.size * 16 + d.size * (2 + 3) + 29 * 8
             pix[lv] += d.size
     return out / max(len(frame_ids), 1), pix / max(len(frame_ids), 1)
+
+
+def mesh_measurement(m, seq, storage, reps=5):
+    """Marching-tetrahedra mesh of the fused map, after the timed region: the
+    extraction time (HIP events around extract_mesh on its stream), its HBM
+    roofline (algorithmic bytes = every live voxel record read once plus the
+    triangles written) and the model accuracy: distance of the unique mesh
+    vertices to the scene's analytic surfaces."""
+    import numpy as np
+    import torch
+    from synth.analytic import scene_distance
+    tris = m.mesh()
+    n = int(tris.shape[0])
+    cap = max(n, 1)
+    buf = torch.empty((cap, 3, 3), dtype=torch.float32, device=m.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=m.device)
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        m.L.extract_mesh(m.h, ctypes.c_void_p(buf.data_ptr()), cap, ctypes.c_void_p(cnt.data_ptr()),
+                         ctypes.c_void_p(stream.cuda_stream))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = float(np.median(ms))
+    _, nb = m.status()
+    rec = {"fp32": 8, "fp16": 4}[storage]
+    alg = nb * 512 * rec + n * 36
+    achieved = alg / (t * 1e-3) / 1e9
+    out = {"triangles": n, "blocks": nb, "extract_ms": round(t, 4), "triangles_per_s": round(n / (t * 1e-3), 1),
+           "roofline": {"kernels": "mesh_count_kernel + mesh_scan_kernel + mesh_write_kernel", "bound": "hbm",
+                        "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes": int(alg), "traffic": None}}
+    if seq.prims is not None and n:
+        V = np.unique(tris.reshape(-1, 3).cpu().numpy().astype(np.float64), axis=0)
+        d = scene_distance(seq.prims, V)
+        out["accuracy"] = {"vertices": int(len(V)), "mean_mm": round(1e3 * float(d.mean()), 3),
+                           "median_mm": round(1e3 * float(np.median(d)), 3),
+                           "p90_mm": round(1e3 * float(np.percentile(d, 90)), 3),
+                           "within_mm": {str(x): round(float((d <= x * 1e-3).mean()), 4) for x in (1, 2, 5, 10, 20)}}
+    return out
 
 
 def make_sequence(workload, n):
@@ -198,6 +242,7 @@ def main():
     ap.add_argument("--unpaced", action="store_true", help="serving: all frames available at once")
     ap.add_argument("--batch", type=int, default=1,
                     help="sessions processed together per step (1..8; the same scene at staggered frames)")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the mesh extraction measurement after the timed region")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for cpu_baseline")
     args = ap.parse_args()
@@ -344,6 +389,8 @@ def main():
                      "blocks_per_launch": int(blocks / max(launches, 1))},
         "map": {"blocks": nblocks, "flags": flags, "final_position_error_m": round(ate_last, 5)},
     }
+    if not args.no_mesh and B == 1:
+        out["mesh"] = mesh_measurement(sessions[0].map, seq, args.storage)
     if not args.no_cpu_baseline and B == 1:
         v, sample = cpu_baseline(seq, args.cpu_budget)
         out["cpu_baseline"] = {"value": round(v, 5), "unit": "frames/s", "cores": 1, "kind": "oracle",

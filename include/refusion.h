@@ -10,7 +10,8 @@
  *   track_frame           (with mask)  refined registration, Sec. III-C
  *   hashmap_allocate                   block allocation incl. carve rays, Sec. III-A/III-D
  *   integrate_frame                    running weighted average + carving, Sec. III-A/III-D
- * and, off the per-frame path, extract_surface (the model the paper meshes).
+ * and, off the per-frame path, extract_surface (zero crossings) and extract_mesh
+ * (the model as a triangle mesh).
  *
  * Conventions shared by every call
  *  - All pointers named d_* and every buffer inside rf_frame are DEVICE
@@ -201,6 +202,21 @@ rf_status compute_dynamic_mask_stages(rf_map* m, const rf_frame* f, const double
  * r, g, b of voxel v, axis); *d_count (device uint32) receives the total
  * number found (may exceed cap; only cap are written).  Order arbitrary. */
 rf_status extract_surface(rf_map* m, float* d_points, uint32_t cap, uint32_t* d_count, void* stream);
+
+/* Triangle mesh of the zero level set (the paper shows its models as meshes,
+ * Sec. I and Fig. 1), by marching tetrahedra: a cube of 8 voxel centres is
+ * meshed when all 8 voxels exist, are observed and hold |sdf| < tau; it is
+ * cut into six tetrahedra along its diagonal (0, a, a|b, 7), inside means
+ * sdf < 0, a crossing on an edge is interpolated linearly from the corner
+ * with the fewer offset bits, and triangles face the positive side.  The
+ * mesh is closed wherever the cubes are.  d_tris: device float32 cap x 9
+ * (three vertices x, y, z in metres, counter-clockwise seen from the
+ * positive side); *d_count (device uint32) receives the total triangle count,
+ * which may exceed cap (then only the first cap are written: call again with
+ * a larger buffer).  Enqueued on stream; uses the map's scratch, so calls on
+ * one map must be ordered with its other calls.  Errors: RF_EINVAL for NULL
+ * map/count or a NULL d_tris with cap > 0. */
+rf_status extract_mesh(rf_map* m, float* d_tris, uint32_t cap, uint32_t* d_count, void* stream);
 
 /* Sticky device flags (RF_FLAG_*) and allocated block count.  Synchronises
  * the stream. */

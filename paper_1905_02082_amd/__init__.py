@@ -277,6 +277,21 @@ class Map:
             return self.surface(cap=n, stream=stream)
         return pts[:n]
 
+    def mesh(self, cap=None, stream=None):
+        """Marching-tetrahedra triangle mesh of the zero level set: (n, 3, 3)
+        float32 device tensor (three vertices x, y, z per triangle, facing the
+        positive side).  cap: triangle capacity of the first attempt."""
+        if cap is None:
+            _, nb = self.status(stream)
+            cap = max(1024, nb * 256)
+        tris = torch.empty((cap, 3, 3), dtype=torch.float32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(self.L.extract_mesh(self.h, _ptr(tris), cap, _ptr(cnt), _stream(stream)), "extract_mesh")
+        n = int(cnt.item())
+        if n > cap:
+            return self.mesh(cap=n, stream=stream)
+        return tris[:n]
+
     def _state_words(self):
         off = (-self.arena.data_ptr()) % 256
         return self.arena[off:off + 80].clone().cpu().view(torch.int64)

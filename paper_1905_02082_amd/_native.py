@@ -73,6 +73,7 @@ EXPORTS = {
                                               ctypes.POINTER(RfMaskParams), c_void_p, c_void_p, c_void_p,
                                               c_void_p, c_void_p, c_void_p]),
     "extract_surface": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
+    "extract_mesh": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "map_status": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_uint32), ctypes.POINTER(c_uint32)]),
     "hashmap_frame_blocks": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "hashmap_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p,

@@ -35,7 +35,7 @@ rf_status check_launch(const char* what) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, total;
+  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, mesh, total;
   uint32_t dirty_cap, tc_tiles;
 };
 
@@ -75,6 +75,7 @@ Layout layout_of(const rf_map_params* p) {
   L.tc_tiles = (p->max_pixels + 255) / 256 + 64;
   L.tcache = o; o = align256(o + (size_t)rf::tile_refs_before(rf::kCacheLevels) * L.tc_tiles * sizeof(rf::BlockRef));
   L.tc_count = o; o = align256(o + (size_t)rf::kCacheLevels * L.tc_tiles * 4);
+  L.mesh = o; o = align256(o + (size_t)2 * rf::kMeshScratch * 4);
   L.total = o;
   return L;
 }
@@ -212,6 +213,7 @@ rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void
   d.dirty = reinterpret_cast<uint32_t*>(a + L.dirty);
   d.tcache = reinterpret_cast<rf::BlockRef*>(a + L.tcache);
   d.tc_count = reinterpret_cast<uint32_t*>(a + L.tc_count);
+  d.mesh_scratch = reinterpret_cast<uint32_t*>(a + L.mesh);
   d.tc_tiles = L.tc_tiles;
   d.max_pixels = p->max_pixels;
   d.dirty_cap = L.dirty_cap;
@@ -372,6 +374,12 @@ rf_status extract_surface(rf_map* m, float* d_points, uint32_t cap, uint32_t* d_
   if (!m || !d_count || (cap && !d_points)) return fail(RF_EINVAL, "map/count/points is NULL");
   rf::launch_surface(m->h.dev, m->h.p.storage, d_points, cap, d_count, S(stream));
   return check_launch("extract_surface");
+}
+
+rf_status extract_mesh(rf_map* m, float* d_tris, uint32_t cap, uint32_t* d_count, void* stream) {
+  if (!m || !d_count || (cap && !d_tris)) return fail(RF_EINVAL, "map/count/triangles is NULL");
+  rf::launch_mesh(m->h.dev, m->h.p.storage, d_tris, cap, d_count, S(stream));
+  return check_launch("extract_mesh");
 }
 
 rf_status map_status(rf_map* m, void* stream, uint32_t* flags, uint32_t* n_blocks) {

@@ -11,6 +11,7 @@
 //   mask scratch max_pixels bytes + two buffers of per-tile dirty flags for the flood fill
 //   tile refs    tracking block cache: per level l < kCacheLevels, tc_tiles x tile_refs(l) x 16 B {key, slot, epoch},
 //                then kCacheLevels x tc_tiles x 4 B pair counts
+//   mesh scratch 2 x kMeshScratch x 4 B
 //
 // Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
 // linear probing, insertion by 64-bit CAS on the key word (insert-only: keys
@@ -56,6 +57,7 @@ struct alignas(16) BlockRef {
   int slot;
   uint32_t epoch;
 };
+constexpr int kMeshScratch = 1024;  // workgroups of the mesh extraction
 constexpr int kCacheLevels = 4;  // pyramid levels with a block cache
 constexpr int kTileRefs = 256;   // largest pair capacity of a tile
 // A 16x16 tile of level l covers 4^l times the area of a level-0 tile, so it
@@ -113,6 +115,7 @@ struct MapDev {
   uint2* integ_counts;  // per integration workgroup: (band, free) updates of the last integration
   BlockRef* tcache;     // tracking block cache (per level: tc_tiles tiles of tile_refs(level) pairs)
   uint32_t* tc_count;   // valid pairs of each cached tile (kCacheLevels x tc_tiles)
+  uint32_t* mesh_scratch;  // mesh extraction: triangles and offsets per workgroup (2 x kMeshScratch)
   uint32_t tc_tiles;    // tiles per level with a cache entry (later tiles look up the hash table only)
   uint32_t* dirty;
   uint32_t max_pixels;

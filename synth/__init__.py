@@ -393,7 +393,7 @@ def large_rooms(n_frames=1000, seed=1905020824, width=640, height=480, n_objects
     # 3 cm truncation and biases registration (about 1 cm per frame at 5 m in this layout)
     return Sequence("large_rooms", width, height, fx, fy, cx, cy, poses, depth, rgb, labels, 0.001,
                     voxel_size=0.005, truncation=0.03, depth_max=3.5, num_buckets=1 << 22,
-                    levels=3, iters=10, carve_stride=2, seed=seed)
+                    levels=3, iters=10, carve_stride=2, seed=seed, prims=P)
 
 
 def depth_metres(seq: Sequence, k: int) -> np.ndarray:
