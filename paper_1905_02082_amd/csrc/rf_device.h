@@ -336,17 +336,9 @@ struct HashSlots {
   }
 };
 
-// Trilinear sample of the TSDF (and, with WANT_COLOUR, of the model intensity)
-// at world point y.  Defined only if all 8 corner voxels lie in allocated
-// blocks and have weight > 0.  Gradients are with respect to world
-// coordinates (d/dg * 1/s).
-// `slots` finds the pool slots of the corner blocks (HashSlots: the hash
-// table; tracking adds a per-tile cache in front of it).
-template <int STORAGE, bool WANT_GRAD, bool WANT_COLOUR, class Slots = HashSlots>
-__device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], float& S, float gS[3],
-                                           float& Iv, float gI[3], const Slots& slots = Slots()) {
-  float fr[3];
-  int i0[3];
+// Voxel cell of world point y: lower corner voxel i0 and fractions fr;
+// false outside the key range.
+__device__ __forceinline__ bool voxel_cell(const MapDev& m, const float y[3], int i0[3], float fr[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float g = y[a] * m.is;
@@ -355,17 +347,24 @@ __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], fl
     i0[a] = (int)fl;
     fr[a] = g - fl;
   }
+  return true;
+}
+
+// The 8 corner records (and colours) of cell i0.  `slots` finds the pool
+// slots of the corner blocks (HashSlots: the hash table; tracking adds a
+// per-tile cache in front of it); false if a corner block is absent.  All
+// loads are issued before any is used, so they share one round trip.  With
+// PIN the empty asm statements pin every loaded value here: without them the
+// compiler sinks each load into the branch that first uses it, which turns
+// the gathers back into a chain of round trips.  Without PIN the loads stay
+// in flight for a later use (a speculative gather).
+template <int STORAGE, bool WANT_COLOUR, bool PIN, class Slots>
+__device__ __forceinline__ bool gather_corners(const MapDev& m, const int i0[3], const Slots& slots, float cs[8],
+                                               float cw[8], uint32_t cc[8]) {
   const int bx0 = i0[0] >> 3, by0 = i0[1] >> 3, bz0 = i0[2] >> 3;
   const int cross = ((i0[0] & 7) == 7 ? 1 : 0) | ((i0[1] & 7) == 7 ? 2 : 0) | ((i0[2] & 7) == 7 ? 4 : 0);
   int sl[8];
   if (!slots(m, bx0, by0, bz0, cross, sl)) return false;
-  // All corner records (and colours) are loaded before any weight is
-  // tested, so the loads share one round trip instead of one each.  The
-  // empty asm statements pin every loaded value to this point: without them
-  // the compiler sinks each load into the branch that first uses it, which
-  // turns the gathers back into a chain of round trips.
-  float cs[8], cw[8], ci[8];
-  uint32_t cc[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
@@ -374,15 +373,28 @@ __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], fl
     VoxelStore<STORAGE>::load(m, idx, cs[k], cw[k]);
     if (WANT_COLOUR) cc[k] = reinterpret_cast<const uint32_t*>(m.rgb)[idx];
   }
+  if (PIN) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    asm volatile("" : "+v"(cs[k]), "+v"(cw[k]));
-    if (WANT_COLOUR) asm volatile("" : "+v"(cc[k]));
+    for (int k = 0; k < 8; ++k) {
+      asm volatile("" : "+v"(cs[k]), "+v"(cw[k]));
+      if (WANT_COLOUR) asm volatile("" : "+v"(cc[k]));
+    }
   }
+  return true;
+}
+
+// Trilinear value (and gradient) of the corner records at fractions fr;
+// defined only if all 8 corners are observed (weight > 0).  Gradients are
+// with respect to world coordinates (d/dg * 1/s).
+template <bool WANT_GRAD, bool WANT_COLOUR>
+__device__ __forceinline__ bool interpolate(const MapDev& m, const float cs[8], const float cw[8],
+                                            const uint32_t cc[8], const float fr[3], float& S, float gS[3],
+                                            float& Iv, float gI[3]) {
   bool observed = true;
 #pragma unroll
   for (int k = 0; k < 8; ++k) observed &= cw[k] > 0.0f;
   if (!observed) return false;
+  float ci[8];
   if (WANT_COLOUR) {
 #pragma unroll
     for (int k = 0; k < 8; ++k)
@@ -403,6 +415,21 @@ __device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], fl
     }
   }
   return true;
+}
+
+// Trilinear sample of the TSDF (and, with WANT_COLOUR, of the model intensity)
+// at world point y.  Defined only if all 8 corner voxels lie in allocated
+// blocks and have weight > 0.
+template <int STORAGE, bool WANT_GRAD, bool WANT_COLOUR, class Slots = HashSlots>
+__device__ __forceinline__ bool sample_map(const MapDev& m, const float y[3], float& S, float gS[3],
+                                           float& Iv, float gI[3], const Slots& slots = Slots()) {
+  float fr[3];
+  int i0[3];
+  if (!voxel_cell(m, y, i0, fr)) return false;
+  float cs[8], cw[8];
+  uint32_t cc[8];
+  if (!gather_corners<STORAGE, WANT_COLOUR, true>(m, i0, slots, cs, cw, cc)) return false;
+  return interpolate<WANT_GRAD, WANT_COLOUR>(m, cs, cw, cc, fr, S, gS, Iv, gI);
 }
 
 }  // namespace rf
