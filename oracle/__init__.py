@@ -66,6 +66,7 @@ def _load():
         "orc_import": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64]),
         "orc_surface": (c_int64, [c_void_p, c_void_p, c_int64]),
         "orc_mesh": (c_int64, [c_void_p, c_void_p, c_int64]),
+        "orc_raycast": (c_int, [c_void_p, P(_Frame), c_void_p, c_double, c_double, c_double, c_int, c_void_p]),
         "orc_se3_exp": (None, [c_void_p, c_void_p]),
         "orc_pose_left_update": (None, [c_void_p, c_void_p]),
         "orc_solve6": (c_int, [c_void_p, c_double, c_void_p]),
@@ -217,6 +218,15 @@ class OracleMap:
         if n:
             self.L.orc_surface(self.h, out.ctypes.data, n)
         return out[:n]
+
+    def raycast(self, fr: Frame, pose, z_near=0.3, z_far=5.0, far_value=5.0, only_invalid=True):
+        """Virtual depth (only_invalid=False) or the frame's depth with its
+        zeros filled (only_invalid=True): (H, W) float32 metres."""
+        T = np.ascontiguousarray(pose, np.float64)
+        out = np.zeros((fr.H, fr.W), np.float32)
+        self.L.orc_raycast(self.h, ctypes.byref(fr.s), T.ctypes.data, z_near, z_far, far_value,
+                           1 if only_invalid else 0, out.ctypes.data)
+        return out
 
     def mesh(self):
         """Marching-tetrahedra triangles (n,3,3): three vertices x, y, z each."""

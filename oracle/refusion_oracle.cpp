@@ -778,6 +778,51 @@ int64_t mesh(const Map<Real>& m, double* out, int64_t cap) {
   return n;
 }
 
+// Virtual depth (Sec. III-E, second option for invalid measurements): a
+// model of the last n frames is ray cast from a frame's registered pose and
+// the zeros of the frame's depth are replaced by the virtual depth, the
+// pixels the model does not explain by a far value.  Reading: along pixel
+// (u, v)'s ray the samples are taken at camera depths z_k = z_near + k step,
+// step = tau / 2 (so the band |sdf| < tau holds at least three samples), for
+// z_k <= z_far, at the back-projection of (u, v) at depth z_k (Eq. 1); the
+// virtual depth is the first crossing from a defined sample S_{k-1} > 0 to a
+// defined sample S_k <= 0, z_{k-1} + step (S_{k-1} / (S_{k-1} - S_k)); 0 if
+// there is none.  With only_invalid, pixels whose raw depth is not zero keep
+// their depth (metres) and the zeros get the virtual depth or far_value;
+// otherwise every pixel gets its virtual depth (0 without a crossing).
+template <class Real>
+void raycast(const Map<Real>& m, const Frame& f, const double* T, Real z_near, Real z_far, Real far_value,
+             bool only_invalid, float* out) {
+  Real R[9], t[3];
+  pose_split<Real>(T, R, t);
+  const Real step = (Real)0.5 * (Real)m.P.truncation;
+  for (int v = 0; v < f.H; ++v)
+    for (int u = 0; u < f.W; ++u) {
+      const float D = depth_at(f, u, v);
+      float& o = out[(size_t)v*f.W + u];
+      if (only_invalid && D != 0.0f) { o = D; continue; }
+      Real hit = 0, prev = 0;
+      bool have_prev = false;
+      for (int k = 0;; ++k) {
+        const Real z = z_near + (Real)k * step;
+        if (!(z <= z_far)) break;
+        Real x[3], y[3];
+        backproject<Real>(f, u, v, z, x);
+        transform(R, t, x, y);
+        Sample<Real> sm = sample_at(m, y);
+        if (!sm.ok) { have_prev = false; continue; }
+        if (have_prev && prev > 0 && sm.S <= 0) {
+          const Real zp = z_near + (Real)(k - 1) * step;
+          hit = zp + step * (prev / (prev - sm.S));
+          break;
+        }
+        prev = sm.S;
+        have_prev = true;
+      }
+      o = only_invalid ? (hit > 0 ? (float)hit : (float)far_value) : (float)hit;
+    }
+}
+
 template <class Real>
 Map<Real>* as(void* h) { return static_cast<Map<Real>*>(static_cast<MapBase*>(h)); }
 
@@ -1011,6 +1056,18 @@ int64_t orc_surface(void* p, double* out, int64_t cap) {
   OrcMap* h = (OrcMap*)p;
   if (h->real_bits == 32) return surface(*as<float>(h->m), out, cap);
   return surface(*as<double>(h->m), out, cap);
+}
+
+// Virtual depth / filled depth of a frame (float32 metres, W*H).
+int orc_raycast(void* p, const orc_frame* fr, const double* T, double z_near, double z_far, double far_value,
+                int only_invalid, float* out) {
+  OrcMap* h = (OrcMap*)p;
+  if (h->real_bits == 32)
+    raycast(*as<float>(h->m), to_frame(fr), T, (float)z_near, (float)z_far, (float)far_value, only_invalid != 0, out);
+  else
+    raycast(*as<double>(h->m), to_frame(fr), T, (double)(float)z_near, (double)(float)z_far, (double)(float)far_value,
+            only_invalid != 0, out);
+  return 0;
 }
 
 // Mesh triangles: 9 doubles each.  Returns the count (writes at most cap).

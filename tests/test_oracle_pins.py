@@ -731,3 +731,88 @@ def test_mesh_fp32_mirror_close_to_fp64():
     T32 = sphere_mesh(c, r, real_bits=32)
     assert T64.shape == T32.shape                   # same cubes, same cases, same emission order
     assert np.abs(T64 - T32).max() < 1e-6
+
+
+# ---------------------------------------------------------------- virtual depth (ray cast)
+
+def plane_map(n, c, s=0.01, tau=0.05, extent=((-0.9, 0.9), (-0.7, 0.7), (0.8, 2.2)), real_bits=64):
+    """Oracle map of the plane n.x = c (SDF positive on the camera side,
+    n pointing away from the camera) over the blocks of a box."""
+    B = 8 * s
+    rng_ = [np.arange(int(np.floor(lo / B)), int(np.floor(hi / B)) + 1) for lo, hi in extent]
+    keys = np.array([[x, y, z] for x in rng_[0] for y in rng_[1] for z in rng_[2]], np.int32)
+    k, sdf, w, rgb = A.fill_map(keys, s, lambda x: np.clip(c - x @ n, -tau, tau))
+    om = O.OracleMap(s, tau, 5.0, 255, 4, real_bits=real_bits)
+    om.import_(k, sdf.astype(np.float32).astype(np.float64), w, rgb)
+    return om
+
+
+def pinhole_frame(W=40, H=30, f=30.0, depth=None):
+    d = np.zeros((H, W), np.float32) if depth is None else depth.astype(np.float32)
+    return O.Frame(d, np.zeros((H, W, 3), np.uint8), f, f, (W - 1) / 2.0, (H - 1) / 2.0)
+
+
+@pytest.mark.parametrize("tilt", [0.0, 0.25, 0.5])
+def test_raycast_of_plane_matches_closed_form(tilt):
+    n = np.array([0.0, np.sin(tilt), np.cos(tilt)])
+    c = 1.3
+    om = plane_map(n, c)
+    fr = pinhole_frame()
+    z = om.raycast(fr, np.eye(4), z_near=0.3, z_far=5.0, only_invalid=False)
+    v, u = np.mgrid[0:fr.H, 0:fr.W]
+    d = np.stack([(u - fr.s.cx) / fr.s.fx, (v - fr.s.cy) / fr.s.fy, np.ones_like(u, float)], -1)
+    exact = c / (d @ n)                              # camera depth of the plane along each ray
+    P = exact[..., None] * d                         # where they meet it
+    inside = ((np.abs(P[..., 0]) < 0.85) & (np.abs(P[..., 1]) < 0.65)
+              & (exact > 0.85) & (exact < 2.1))       # inside the mapped box, two voxels from its faces
+    assert inside.sum() > 500
+    # the plane's TSDF is linear, so the trilinear samples and the crossing are exact up to rounding
+    assert np.abs(z[inside] - exact[inside]).max() < 2e-6
+
+
+def test_raycast_of_sphere_matches_ray_intersection():
+    s, tau = 0.01, 0.05
+    c, r = np.array([0.05, -0.03, 1.2]), 0.3
+    ang = np.linspace(0, 2 * np.pi, 90)
+    pol = np.linspace(0, np.pi, 45)
+    pts = c + r * np.array([[np.cos(a) * np.sin(b), np.sin(a) * np.sin(b), np.cos(b)] for a in ang for b in pol])
+    keys = A.blocks_near(pts, s, 1)
+    k, sdf, w, rgb = A.fill_map(keys, s, lambda x: np.clip(np.linalg.norm(x - c, axis=-1) - r, -tau, tau))
+    om = O.OracleMap(s, tau, 5.0, 255, 4, real_bits=64)
+    om.import_(k, sdf, w, rgb)
+    fr = pinhole_frame(W=48, H=36, f=40.0)
+    z = om.raycast(fr, np.eye(4), only_invalid=False)
+    v, u = np.mgrid[0:fr.H, 0:fr.W]
+    d = np.stack([(u - fr.s.cx) / fr.s.fx, (v - fr.s.cy) / fr.s.fy, np.ones_like(u, float)], -1)
+    # first intersection of z d with the sphere: |z d - c|^2 = r^2
+    a = (d * d).sum(-1)
+    b = (d @ c)
+    disc = b * b - a * (c @ c - r * r)
+    exact = (b - np.sqrt(np.maximum(disc, 0))) / a
+    nrm = (exact[..., None] * d - c) / r
+    cosi = np.abs((nrm * d).sum(-1)) / np.sqrt(a)
+    hitp = (disc > 0) & (cosi > 0.5)                 # rays meeting the sphere at incidence below 60 degrees
+    assert hitp.sum() > 100
+    assert np.abs(z[hitp] - exact[hitp]).max() < 1e-3
+    assert (z[~(disc > 0)] == 0).all()               # rays that miss report no crossing
+
+
+def test_raycast_fills_only_zero_depth():
+    n, c = np.array([0.0, 0.0, 1.0]), 1.3
+    om = plane_map(n, c)
+    rng = np.random.default_rng(3)
+    depth = rng.uniform(0.5, 4.0, (30, 40)).astype(np.float32)
+    holes = rng.uniform(size=depth.shape) < 0.3
+    depth[holes] = 0.0
+    depth[0, :] = 0.0                                # top row: rays through the mapped box
+    fr = pinhole_frame(depth=depth)
+    out = om.raycast(fr, np.eye(4), far_value=4.5, only_invalid=True)
+    assert np.array_equal(out[~holes & (np.arange(30)[:, None] > 0)], depth[~holes & (np.arange(30)[:, None] > 0)])
+    filled = out[depth == 0]
+    assert np.all((np.abs(filled - 1.3) < 2e-6) | (filled == np.float32(4.5)))
+    assert (np.abs(filled - 1.3) < 2e-6).mean() > 0.9
+    # a camera looking away from the model gets the far value everywhere it had zeros
+    away = np.diag([1.0, 1.0, -1.0, 1.0])
+    away[0, 0] = -1.0
+    out2 = om.raycast(fr, away, far_value=4.5, only_invalid=True)
+    assert np.all(out2[depth == 0] == np.float32(4.5))
