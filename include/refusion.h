@@ -10,8 +10,8 @@
  *   track_frame           (with mask)  refined registration, Sec. III-C
  *   hashmap_allocate                   block allocation incl. carve rays, Sec. III-A/III-D
  *   integrate_frame                    running weighted average + carving, Sec. III-A/III-D
- * and, off the per-frame path, extract_surface (zero crossings) and extract_mesh
- * (the model as a triangle mesh).
+ * and, off the per-frame path, extract_surface (zero crossings), extract_mesh
+ * (the model as a triangle mesh) and raycast_depth (virtual depth, Sec. III-E).
  *
  * Conventions shared by every call
  *  - All pointers named d_* and every buffer inside rf_frame are DEVICE
@@ -217,6 +217,23 @@ rf_status extract_surface(rf_map* m, float* d_points, uint32_t cap, uint32_t* d_
  * one map must be ordered with its other calls.  Errors: RF_EINVAL for NULL
  * map/count or a NULL d_tris with cap > 0. */
 rf_status extract_mesh(rf_map* m, float* d_tris, uint32_t cap, uint32_t* d_count, void* stream);
+
+/* Virtual depth by ray casting the model (Sec. III-E, the second way to treat
+ * invalid measurements: a model of the last n frames is cast from each
+ * frame's registered pose and the frame's zero depths are replaced).  Along
+ * pixel (u, v)'s ray the model is sampled (trilinear, defined where all 8
+ * corner voxels are observed) at camera depths z_k = z_near + k tau/2,
+ * z_k <= z_far; the virtual depth is the first crossing from a defined
+ * sample S > 0 to the next defined sample S' <= 0, z + (tau/2) S / (S - S'),
+ * or 0 without one.  f: the frame (intrinsics, size; its depth is read only
+ * with only_invalid); d_pose: device float64 4x4 camera->world.  d_out:
+ * device float32 width*height metres.  only_invalid = 1: pixels whose depth
+ * is not zero keep it (in metres) and the zeros get the virtual depth, or
+ * far_value where the ray meets no surface; only_invalid = 0: the virtual
+ * depth of every pixel.  Errors: RF_EINVAL for NULL pointers, a bad frame,
+ * z_near <= 0, z_far <= z_near, far_value < 0 or only_invalid not 0/1. */
+rf_status raycast_depth(rf_map* m, const rf_frame* f, const double* d_pose, float z_near, float z_far,
+                        float far_value, int32_t only_invalid, float* d_out, void* stream);
 
 /* Sticky device flags (RF_FLAG_*) and allocated block count.  Synchronises
  * the stream. */

@@ -21,7 +21,7 @@ from ._native import (RF_DEPTH_F32, RF_DEPTH_U16, RF_FLAG_HASH_FULL, RF_FLAG_MAS
                       RF_STORAGE_FP16_U8, RF_STORAGE_FP32)
 
 __all__ = ["MapParams", "TrackParams", "MaskParams", "Frame", "Map", "Session", "Pipeline", "process_batch",
-           "GraphStep", "RefusionError", "hashmap_bytes", "lib"]
+           "GraphStep", "VirtualDepth", "RefusionError", "hashmap_bytes", "lib"]
 
 
 class RefusionError(RuntimeError):
@@ -277,6 +277,21 @@ class Map:
             return self.surface(cap=n, stream=stream)
         return pts[:n]
 
+    def raycast(self, frame: Frame, pose: torch.Tensor, z_near=0.3, z_far=None, far_value=None, only_invalid=True,
+                out=None, stream=None):
+        """Virtual depth of the model seen from pose (float64 4x4 device):
+        (H, W) float32 metres.  only_invalid: the frame's depth with its zeros
+        replaced by the virtual depth (far_value where no surface is met)."""
+        _dev(pose, "pose", torch.float64, (4, 4))
+        z_far = self.params.depth_max if z_far is None else z_far
+        far_value = self.params.depth_max if far_value is None else far_value
+        if out is None:
+            out = torch.empty((frame.H, frame.W), dtype=torch.float32, device=self.device)
+        _dev(out, "out", torch.float32, (frame.H, frame.W))
+        _check(self.L.raycast_depth(self.h, ctypes.byref(frame.s), _ptr(pose), z_near, z_far, far_value,
+                                    1 if only_invalid else 0, _ptr(out), _stream(stream)), "raycast_depth")
+        return out
+
     def mesh(self, cap=None, stream=None):
         """Marching-tetrahedra triangle mesh of the zero level set: (n, 3, 3)
         float32 device tensor (three vertices x, y, z per triangle, facing the
@@ -477,6 +492,41 @@ class GraphStep:
                 events[5].record(stream)
         for s in self.sessions:
             s.k += 1
+
+
+class VirtualDepth:
+    """The second way of the paper to treat invalid depth (Sec. III-E): frames
+    are collected n at a time; a temporary model is fused from them at their
+    registered poses and cast from each pose, and each frame's zero depths are
+    replaced by the virtual depth, or far_value where the rays meet no
+    surface.  push() returns the n refined frames (float32 metres, same
+    colour) once n have been collected, so the model they feed lags n frames.
+    The temporary model reuses one arena."""
+
+    def __init__(self, params: MapParams, n=10, z_near=0.3, far_value=None, device="cuda"):
+        self.n = n
+        self.z_near = z_near
+        self.far_value = params.depth_max if far_value is None else far_value
+        self.temp = Map(params, device)
+        self.pending = []
+
+    def push(self, frame: Frame, pose: torch.Tensor, stream=None):
+        _dev(pose, "pose", torch.float64, (4, 4))
+        self.pending.append((frame, pose.clone()))
+        if len(self.pending) < self.n:
+            return []
+        L = self.temp.L
+        _check(L.hashmap_reset(self.temp.h, _stream(stream)), "hashmap_reset")
+        for f, P in self.pending:
+            self.temp.allocate(f, P, stream=stream)
+            self.temp.integrate(f, P, stream=stream)
+        out = []
+        for f, P in self.pending:
+            d = self.temp.raycast(f, P, z_near=self.z_near, far_value=self.far_value, only_invalid=True,
+                                  stream=stream)
+            out.append((Frame(d, f.rgb, f.fx, f.fy, f.cx, f.cy, 1.0), P))
+        self.pending = []
+        return out
 
 
 class Pipeline:

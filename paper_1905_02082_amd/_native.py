@@ -74,6 +74,8 @@ EXPORTS = {
                                               c_void_p, c_void_p, c_void_p]),
     "extract_surface": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "extract_mesh": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
+    "raycast_depth": (c_int32, [c_void_p, c_void_p, c_void_p, c_float, c_float, c_float, c_int32, c_void_p,
+                                c_void_p]),
     "map_status": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_uint32), ctypes.POINTER(c_uint32)]),
     "hashmap_frame_blocks": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "hashmap_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p,

@@ -376,6 +376,20 @@ rf_status extract_surface(rf_map* m, float* d_points, uint32_t cap, uint32_t* d_
   return check_launch("extract_surface");
 }
 
+rf_status raycast_depth(rf_map* m, const rf_frame* f, const double* d_pose, float z_near, float z_far,
+                        float far_value, int32_t only_invalid, float* d_out, void* stream) {
+  if (!m || !f || !d_pose || !d_out) return fail(RF_EINVAL, "map/frame/pose/out is NULL");
+  if (!(z_near > 0.0f) || !(z_far > z_near) || !(far_value >= 0.0f))
+    return fail(RF_EINVAL, "need 0 < z_near < z_far and far_value >= 0");
+  if (only_invalid != 0 && only_invalid != 1) return fail(RF_EINVAL, "only_invalid must be 0 or 1");
+  rf::FrameDev fd;
+  rf_status st = make_frame(f, fd);
+  if (st) return st;
+  rf::launch_raycast(m->h.dev, fd, f->depth_format, m->h.p.storage, d_pose, z_near, z_far, far_value, only_invalid,
+                     d_out, S(stream));
+  return check_launch("raycast_depth");
+}
+
 rf_status extract_mesh(rf_map* m, float* d_tris, uint32_t cap, uint32_t* d_count, void* stream) {
   if (!m || !d_count || (cap && !d_tris)) return fail(RF_EINVAL, "map/count/triangles is NULL");
   rf::launch_mesh(m->h.dev, m->h.p.storage, d_tris, cap, d_count, S(stream));

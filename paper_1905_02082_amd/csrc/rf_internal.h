@@ -70,6 +70,8 @@ void launch_mask(Batch& b, int depth_format, int storage, const rf_mask_params& 
 void launch_map_init(const MapDev& m, uint32_t num_buckets, int storage, hipStream_t s);
 void launch_surface(const MapDev& m, int storage, float* pts, uint32_t cap, uint32_t* count, hipStream_t s);
 void launch_mesh(const MapDev& m, int storage, float* tris, uint32_t cap, uint32_t* count, hipStream_t s);
+void launch_raycast(const MapDev& m, const FrameDev& f, int depth_format, int storage, const double* pose,
+                    float z_near, float z_far, float far_value, int only_invalid, float* out, hipStream_t s);
 void launch_frame_blocks(const MapDev& m, int32_t* keys, uint32_t cap, uint32_t* count, hipStream_t s);
 void launch_export(const MapDev& m, int storage, int32_t* keys, float* sdf, float* w, uint8_t* rgb,
                    uint32_t cap, uint32_t* count, hipStream_t s);
