@@ -9,10 +9,11 @@
 // only_invalid the pixels whose depth is not zero keep it (metres) and only
 // the zeros are cast, getting the virtual depth or far_value.
 //
-// A thread keeps the pool slots of the 2x2x2 blocks above the block of its
-// last sample's lower corner, so the hash table is probed only when the ray
+// A thread keeps the pool slots of the 2x2x2 blocks above the block of a
+// sample's lower corner, so the hash table is probed only when the ray
 // enters a new block (about one sample in five); absent blocks are kept as
-// -1.  Every defined sample costs one round trip for its 8 corner records.
+// -1.  The corner records of up to kRaySamples consecutive samples whose
+// corners lie in that neighbourhood are loaded together (one round trip).
 #include "rf_device.h"
 #include "rf_internal.h"
 
@@ -39,6 +40,8 @@ __device__ __forceinline__ void neighbourhood_slots(const MapDev& m, int bx, int
   }
 }
 
+constexpr int kRaySamples = 2;  // samples whose corner records are loaded together (2 measured best of 1, 2, 4, 8)
+
 template <int DF, int STORAGE>
 __global__ __launch_bounds__(256) void raycast_kernel(MapDev m, FrameDev f, const double* pose, float z_near,
                                                       float z_far, float far_value, int only_invalid, float* out) {
@@ -58,50 +61,87 @@ __global__ __launch_bounds__(256) void raycast_kernel(MapDev m, FrameDev f, cons
   bool have_prev = false;
   int base[3] = {INT_MIN, INT_MIN, INT_MIN};
   int sl[8];
-  for (int k = 0;; ++k) {
-    const float z = z_near + (float)k * step;
-    if (!(z <= z_far)) break;
-    const float x[3] = {ru * z, rv * z, z};
-    float y[3];
-    xform(R, t, x, y);
-    int i0[3];
-    float fr[3];
-    bool defined = voxel_cell(m, y, i0, fr);
-    float S = 0.0f;
-    if (defined) {
-      const int b0[3] = {i0[0] >> 3, i0[1] >> 3, i0[2] >> 3};
-      if (b0[0] != base[0] || b0[1] != base[1] || b0[2] != base[2]) {
-        base[0] = b0[0];
-        base[1] = b0[1];
-        base[2] = b0[2];
-        neighbourhood_slots(m, b0[0], b0[1], b0[2], sl);
+  // Samples go in batches: the first sample of a batch fixes the 2x2x2 block
+  // neighbourhood (probed if it changed), the batch runs on while the
+  // following samples' corners stay inside it (at most kRaySamples), the
+  // corner records of the whole batch are loaded together, and the batch's
+  // samples are then tested in order, exactly as one at a time.
+  int k = 0;
+  while (true) {
+    const float z0 = z_near + (float)k * step;
+    if (!(z0 <= z_far)) break;
+    int i0[kRaySamples][3];
+    float fr[kRaySamples][3];
+    bool ok[kRaySamples];
+    int nb = 0;  // samples in this batch
+#pragma unroll
+    for (int q = 0; q < kRaySamples; ++q) {
+      const float z = z_near + (float)(k + q) * step;
+      const float x[3] = {ru * z, rv * z, z};
+      float y[3];
+      xform(R, t, x, y);
+      ok[q] = (z <= z_far) && voxel_cell(m, y, i0[q], fr[q]);
+      if (q == 0) {
+        if (ok[0]) {
+          const int b0[3] = {i0[0][0] >> 3, i0[0][1] >> 3, i0[0][2] >> 3};
+          if (b0[0] != base[0] || b0[1] != base[1] || b0[2] != base[2]) {
+            base[0] = b0[0];
+            base[1] = b0[1];
+            base[2] = b0[2];
+            neighbourhood_slots(m, b0[0], b0[1], b0[2], sl);
+          }
+        }
+        nb = 1;
+      } else if (nb == q) {
+        // corners of sample q inside the neighbourhood: (i0 >> 3) and ((i0 + 1) >> 3) - base in {0, 1}
+        bool in = ok[q] && ok[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int lo = (i0[q][a] >> 3) - base[a], hi = ((i0[q][a] + 1) >> 3) - base[a];
+          in = in && lo >= 0 && hi <= 1;
+        }
+        if (in) nb = q + 1;
       }
-      const int cross = ((i0[0] & 7) == 7 ? 1 : 0) | ((i0[1] & 7) == 7 ? 2 : 0) | ((i0[2] & 7) == 7 ? 4 : 0);
-      float cs[8], cw[8];
+    }
+    float cs[kRaySamples][8], cw[kRaySamples][8];
+    bool got[kRaySamples];
+#pragma unroll
+    for (int q = 0; q < kRaySamples; ++q) {
+      got[q] = q < nb && ok[q];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const int s = sl[c & cross];
-        defined &= s >= 0;
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+        const int o = (((i0[q][0] + dx) >> 3) - base[0]) | ((((i0[q][1] + dy) >> 3) - base[1]) << 1) |
+                      ((((i0[q][2] + dz) >> 3) - base[2]) << 2);
+        const int s = got[q] ? sl[o & 7] : -1;
+        got[q] = got[q] && s >= 0;
         const uint32_t vi = (uint32_t)(s >= 0 ? s : 0) * 512u +
-                            (uint32_t)(((i0[0] + (c & 1)) & 7) + 8 * ((i0[1] + ((c >> 1) & 1)) & 7) +
-                                       64 * ((i0[2] + (c >> 2)) & 7));
-        VoxelStore<STORAGE>::load(m, vi, cs[c], cw[c]);
+                            (uint32_t)(((i0[q][0] + dx) & 7) + 8 * ((i0[q][1] + dy) & 7) + 64 * ((i0[q][2] + dz) & 7));
+        VoxelStore<STORAGE>::load(m, vi, cs[q][c], cw[q][c]);
       }
-      float gS[3], Iv, gI[3];
+    }
+    bool done = false;
+#pragma unroll
+    for (int q = 0; q < kRaySamples; ++q) {
+      if (done || q >= nb) continue;
+      float S = 0.0f, gS[3], Iv, gI[3];
       uint32_t cc[8];
-      defined = defined && interpolate<false, false>(m, cs, cw, cc, fr, S, gS, Iv, gI);
+      const bool defined = got[q] && interpolate<false, false>(m, cs[q], cw[q], cc, fr[q], S, gS, Iv, gI);
+      if (!defined) {
+        have_prev = false;
+        continue;
+      }
+      if (have_prev && prev > 0.0f && S <= 0.0f) {
+        const float zp = z_near + (float)(k + q - 1) * step;
+        hit = zp + step * (prev / (prev - S));
+        done = true;
+        continue;
+      }
+      prev = S;
+      have_prev = true;
     }
-    if (!defined) {
-      have_prev = false;
-      continue;
-    }
-    if (have_prev && prev > 0.0f && S <= 0.0f) {
-      const float zp = z_near + (float)(k - 1) * step;
-      hit = zp + step * (prev / (prev - S));
-      break;
-    }
-    prev = S;
-    have_prev = true;
+    if (done) break;
+    k += nb;
   }
   out[idx] = only_invalid ? (hit > 0.0f ? hit : far_value) : hit;
 }
