@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void raycast_kernel(MapDev m, FrameDev f, cons
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= f.W * f.H) return;
   const int u = idx % f.W, v = idx / f.W;
-  const float D = load_depth<DF>(f, idx);
+  const float D = only_invalid ? load_depth<DF>(f, idx) : 0.0f;  // the depth is read only to fill it
   if (only_invalid && D != 0.0f) {
     out[idx] = D;
     return;
