@@ -115,6 +115,22 @@ def test_null_handles_rejected(N):
     assert L.track_frame(None, None, None, None, None, None, None) == N.RF_EINVAL
     assert L.compute_dynamic_mask(None, None, None, None, None, None, None) == N.RF_EINVAL
     assert L.map_status(None, None, None, None) == N.RF_EINVAL
+    assert L.extract_mesh(None, None, 0, None, None) == N.RF_EINVAL
+    assert L.raycast_depth(None, None, None, 0.3, 5.0, 5.0, 1, None, None) == N.RF_EINVAL
+
+
+def test_raycast_and_mesh_argument_checks(N):
+    """Bad ray-cast ranges and a NULL triangle buffer with a capacity are
+    rejected on the host, before anything is enqueued (the map handle is a
+    dummy pointer that is never dereferenced by these checks)."""
+    L = N.load()
+    fake = ctypes.c_void_p(0x1000)
+    fr = N.RfFrame(100.0, 100.0, 40.0, 30.0, 80, 60, 0x2000, N.RF_DEPTH_F32, 1.0, 0x3000)
+    pose, out = ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000)
+    for zn, zf, far, only in [(0.0, 5.0, 5.0, 1), (0.5, 0.4, 5.0, 1), (0.3, 5.0, -1.0, 1), (0.3, 5.0, 5.0, 2)]:
+        assert L.raycast_depth(fake, ctypes.byref(fr), pose, zn, zf, far, only, out, None) == N.RF_EINVAL
+        assert L.rf_last_error().decode()
+    assert L.extract_mesh(fake, None, 10, ctypes.c_void_p(0x6000), None) == N.RF_EINVAL
 
 
 def test_package_has_no_cpu_fallback():

@@ -70,10 +70,11 @@ def test_raycast_of_analytic_map_matches_oracle(rf, shape):
     assert np.abs(zg[both] - z64[both]).max() < 1e-4              # FP64 reference
 
 
-def test_raycast_of_fused_map_fills_holes_like_the_oracle(rf):
+@pytest.mark.parametrize("storage,orc_storage", [("fp32", 0), ("fp16", 1)])
+def test_raycast_of_fused_map_fills_holes_like_the_oracle(rf, storage, orc_storage):
     seq = synth.parity_room(n_frames=5)
-    m = rf.Map(map_params(rf, seq))
-    o64, o32 = oracle_maps(seq)
+    m = rf.Map(map_params(rf, seq, storage))
+    o64, o32 = oracle_maps(seq, orc_storage)
     for k in range(4):
         g = gpu_frame(rf, seq, k)
         P = dev_pose(seq.poses[k])
