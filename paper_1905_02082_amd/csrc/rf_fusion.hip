@@ -37,8 +37,8 @@ __device__ __forceinline__ bool leads_run(unsigned long long key, bool valid, un
 // Block-grid DDA of segment q0 -> q1 (block units): cells c = floor(q0) ...
 // e = floor(q1), exactly |e-c|_1 steps, each along the axis with the smallest
 // next-boundary parameter among the axes not yet at e (ties: x, y, z).  Cells
-// are produced in batches of 8 whose home buckets are loaded together, so a
-// ray costs one hash round trip per 8 cells instead of one per cell.
+// are produced in batches of 12 whose home buckets are loaded together, so a
+// ray costs one hash round trip per 12 cells instead of one per cell.
 struct Dda {
   int c[3], e[3], step[3];
   float tmax[3], tdel[3];
@@ -86,10 +86,10 @@ struct Dda {
 
 template <int DF>
 __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
-  // Per job: workgroups [0, band_groups) take the band segments of the pixels
-  // that are not on the carve grid; the rest take the carve segments of the
-  // carve-grid pixels, so the long rays share wavefronts with rays of similar
-  // length.
+  // Per job: workgroups [0, carve_groups) take the carve segments of the
+  // carve-grid pixels, the rest the band segments of the other pixels, so the
+  // long rays share wavefronts with rays of similar length; the carve
+  // workgroups come first so that the longest chains start first.
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const MapDev& m = J.m;
@@ -97,17 +97,17 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
   const int g = blockIdx.x - b.base[jb];
   int u, v;
   const int s_c = (int)m.carve_stride;
-  if (g < J.band_groups) {
-    const int idx = g * blockDim.x + threadIdx.x;
+  if (g < J.carve_groups) {
+    const int j = g * blockDim.x + threadIdx.x;
+    if (j >= J.carve_w * J.carve_h) return;
+    u = (j % J.carve_w) * s_c;
+    v = (j / J.carve_w) * s_c;
+  } else {
+    const int idx = (g - J.carve_groups) * blockDim.x + threadIdx.x;
     if (idx >= f.W * f.H) return;
     u = idx % f.W;
     v = idx / f.W;
     if (u % s_c == 0 && v % s_c == 0) return;
-  } else {
-    const int j = (g - J.band_groups) * blockDim.x + threadIdx.x;
-    if (j >= J.carve_w * J.carve_h) return;
-    u = (j % J.carve_w) * s_c;
-    v = (j / J.carve_w) * s_c;
   }
   const uint8_t* mask = J.mask;
   const double* pose = J.pose;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
   }
   Dda d;
   d.init(q0, q1);
-  constexpr int kBatch = 8;
+  constexpr int kBatch = 12;
   while (d.left > 0) {
     int cx[kBatch], cy[kBatch], cz[kBatch];
     bool ok[kBatch];
@@ -389,11 +389,11 @@ void launch_allocate(Batch& b, int depth_format, hipStream_t s) {
     Job& J = b.job[j];
     const int n = J.f.W * J.f.H;
     const int sc = (int)J.m.carve_stride;
-    J.band_groups = (n + 255) / 256;
     J.carve_w = (J.f.W + sc - 1) / sc;
     J.carve_h = (J.f.H + sc - 1) / sc;
+    J.carve_groups = (J.carve_w * J.carve_h + 255) / 256;
     b.base[j] = total;
-    total += J.band_groups + (J.carve_w * J.carve_h + 255) / 256;
+    total += J.carve_groups + (n + 255) / 256;
   }
   b.base[b.n] = total;
   if (depth_format == RF_DEPTH_U16) alloc_kernel<RF_DEPTH_U16><<<total, 256, 0, s>>>(b);

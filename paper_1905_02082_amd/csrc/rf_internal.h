@@ -31,7 +31,7 @@ struct Job {
   uint8_t* filled;
   float* residual;
   int tiles_x, tiles_y;     // flood-fill tile grid
-  int band_groups;          // allocation: workgroups of band rays
+  int carve_groups;         // allocation: workgroups of carve rays (before the band rays')
   int carve_w, carve_h;     // allocation: carve-grid size
 };
 
