@@ -222,13 +222,25 @@ __global__ void reset_frame_list_kernel(Batch b) {
 // Integration of one frame into the blocks of the frame list (Sec. III-A
 // running average, Sec. III-D carving).  Workgroups stride over the list and
 // take kIntegBlocks listed blocks per step; a thread owns voxels l and l + 256
-// of each.  Every load a step needs is issued before any result is used: the
-// list entries and buckets (uniform, one round trip each for all the step's
-// blocks), then the depth, the mask byte and the voxel record of every voxel
-// together.  The record is read even for voxels the frame leaves untouched
-// (about a fifth of a listed block), which costs those bytes but saves a
-// dependent round trip; only voxels the frame updates are written.
+// of each.  The list entries and buckets of a step (uniform) are fetched
+// during the step before it; a step issues the depth, the mask byte and the
+// voxel record of every voxel together before any is used.  The record is
+// read even for voxels the frame leaves untouched (about a fifth of a listed
+// block), which costs those bytes but saves a dependent round trip; only
+// voxels the frame updates are written.
 constexpr int kIntegBlocks = 2;
+
+// Bucket i (key, slot) of the wavefront's lane i, for i < N.
+template <int N>
+__device__ __forceinline__ void take_lanes(unsigned long long key, uint32_t slot, Bucket (&out)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)key, i);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(key >> 32), i);
+    out[i].key = ((unsigned long long)hi << 32) | lo;
+    out[i].slot = __builtin_amdgcn_readlane(slot, i);
+  }
+}
 
 template <int DF, int STORAGE>
 __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
@@ -245,16 +257,31 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   float R[9], t[3];
   load_pose_f(J.pose, R, t);
   uint32_t nb = 0, nf = 0;
-  for (uint32_t f0 = g0; f0 < nF; f0 += kIntegBlocks * gn) {
-    uint32_t hb[kIntegBlocks];
-#pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) {
-      const uint32_t fi = f0 + i * gn;
-      hb[i] = m.flist[fi < nF ? fi : f0];
-    }
+  const uint32_t stride = kIntegBlocks * gn;
+  // The list entries and buckets of a step are fetched during the step before
+  // it (the list entries while its voxel gathers are in flight, the buckets
+  // after them), so a step waits on two round trips instead of four.  Lane i
+  // of each wavefront fetches listed block i (i < kIntegBlocks; the other
+  // lanes repeat the last), and the step reads the buckets out of lane i once
+  // its colour loads have returned, before its stores of colour, so the next
+  // step starts without waiting for those stores.
+  const int lane = threadIdx.x & 63;
+  const uint32_t my_i = (uint32_t)min(lane, kIntegBlocks - 1);
+  Bucket cur[kIntegBlocks];
+  if (g0 < nF) {
+    const uint32_t fi = g0 + my_i * gn;
+    const Bucket bq = m.buckets[m.flist[fi < nF ? fi : g0]];
+    take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
+  }
+  for (uint32_t f0 = g0; f0 < nF; f0 += stride) {
     Bucket bu[kIntegBlocks];
 #pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) bu[i] = m.buckets[hb[i]];
+    for (int i = 0; i < kIntegBlocks; ++i) bu[i] = cur[i];
+    // the next step's list entries (past the list's end: this step's first
+    // entry again, so the loads stay unconditional and in bounds)
+    const uint32_t f1 = f0 + stride;
+    const uint32_t fn = f1 + my_i * gn;
+    const uint32_t hn = m.flist[fn < nF ? fn : f0];
     int pix[NV];
     uint32_t vidx[NV];
     float X2[NV];
@@ -284,23 +311,19 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       vis[v] = in;
     }
     float D[NV], sdf[NV], W[NV];
-    uint32_t mk[NV], cpx[NV][3];
+    uint32_t mk[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       D[v] = load_depth<DF>(f, pix[v]);
       mk[v] = mask_src[pix[v]];
       VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
-      const uint8_t* px = f.rgb + 3 * pix[v];  // the frame's colour (used by band voxels)
-      cpx[v][0] = px[0];
-      cpx[v][1] = px[1];
-      cpx[v][2] = px[2];
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      asm volatile("" : "+v"(D[v]), "+v"(mk[v]), "+v"(sdf[v]), "+v"(W[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]),
-                   "+v"(cpx[v][2]));
+    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(D[v]), "+v"(mk[v]), "+v"(sdf[v]), "+v"(W[v]));
+    const Bucket bq = m.buckets[hn];  // the next step's buckets
     // sdf and weight of every updated voxel; the band voxels then update
-    // their colour, with all colour loads of the step issued together
+    // their colour, with all colour loads of the step (the voxel's and the
+    // frame's) issued together
     bool band[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -316,14 +339,21 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       nb += band[v];
       nf += !band[v];
     }
-    uint32_t cold[NV];
+    uint32_t cold[NV], cpx[NV][3];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       cold[v] = 0u;
-      if (band[v]) cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
+      cpx[v][0] = cpx[v][1] = cpx[v][2] = 0u;
+      if (!band[v]) continue;
+      cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
+      const uint8_t* px = f.rgb + 3 * pix[v];
+      cpx[v][0] = px[0];
+      cpx[v][1] = px[1];
+      cpx[v][2] = px[2];
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]));
+    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]), "+v"(cpx[v][2]));
+    take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if (!band[v]) continue;
