@@ -41,18 +41,19 @@ def log(*a):
 
 
 def traffic_from_profile(kernel, workload, storage):
-    """HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) per launch of `kernel`
-    from the committed rocprofv3 PMC summary, if it was taken on the current
-    kernel source (else None)."""
+    """(HBM bytes per launch, L2 hit rate) of `kernel` from the committed
+    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, calibrated; TCC_HIT /
+    (TCC_HIT + TCC_MISS)), if it was taken on the current kernel source
+    (else None, None)."""
     path = os.path.join(ROOT, "profiles", "%s_%s_%s_pmc.json" % (kernel.replace("_kernel", ""), workload, storage))
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as fh:
         d = json.load(fh)
     from paper_1905_02082_amd.profiling import kernel_source_hash
     if d.get("kernel_source_hash") != kernel_source_hash(kernel):
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return None, None
+    return d.get("hbm_bytes_per_launch"), d.get("l2_hit_rate")
 
 
 def track_footprint(seq, block_keys, frame_ids, storage):
@@ -372,8 +373,9 @@ def main():
     alg_per_launch = alg_bytes / max(launches, 1)
     integ_ms = float(per_stage[:, 4].mean())
     achieved = alg_per_launch / (integ_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile("integrate_kernel", args.workload, args.storage) if B == 1 else None
-    track_traffic = traffic_from_profile("track_kernel", args.workload, args.storage) if B == 1 else None
+    traffic, l2_hit = traffic_from_profile("integrate_kernel", args.workload, args.storage) if B == 1 else (None, None)
+    track_traffic, track_l2_hit = (traffic_from_profile("track_kernel", args.workload, args.storage) if B == 1
+                                   else (None, None))
 
     # trajectory error against the generator's ground truth (context only)
     E = np.linalg.inv(seq.poses[n - 1]) @ T_final       # session 0
@@ -405,6 +407,7 @@ def main():
         "roofline": {"kernel": "track_kernel", "bound": "hbm", "achieved": round(track_achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(track_achieved / HBM_PEAK_GBS, 4),
                      "traffic": track_traffic,
+                     "l2_hit_rate": track_l2_hit,
                      "alg_bytes_per_launch": int(track_alg),
                      "avg_launch_ms": round(track_ms, 5),
                      "launches_per_step": 2 * sweeps,
@@ -412,6 +415,7 @@ def main():
         "roofline_integrate": {"kernel": "integrate_kernel", "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "l2_hit_rate": l2_hit,
                      "alg_bytes_per_launch": int(alg_per_launch),
                      "avg_launch_ms": round(integ_ms, 5),
                      "band_updates_per_launch": int(band / max(launches, 1)),

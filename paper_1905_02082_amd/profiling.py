@@ -9,13 +9,16 @@
       size, e.g. per pyramid level) from the rocprofv3 database under DIR.
   python -m paper_1905_02082_amd.profiling pmc --fetch DIR --write DIR
          --copy-fetch DIR --copy-write DIR --kernel REGEX --skip N
-         [--copy-mib 1024] [--json OUT --name KERNEL --workload W --storage S]
+         [--l2 DIR] [--copy-mib 1024] [--json OUT --name KERNEL --workload W --storage S]
       HBM bytes per dispatch of the kernels matching REGEX: FETCH_SIZE and
       WRITE_SIZE (KiB per dispatch, each from its own rocprofv3 --pmc run)
       scaled by the factor that makes the same counter read the known size of
       the calibration copy; the first N matching dispatches are skipped
-      (warmup).  With --json, writes the figure with the hash of the kernel's
-      sources, so a later edit of the kernel invalidates it.
+      (warmup).  With --l2, also the L2 hit rate TCC_HIT / (TCC_HIT +
+      TCC_MISS) over the same dispatches, from a run with
+      --pmc TCC_HIT_sum TCC_MISS_sum.  With --json, writes the figures with the
+      hash of the kernel's sources, so a later edit of the kernel invalidates
+      them.
 """
 from __future__ import annotations
 
@@ -115,6 +118,13 @@ def pmc(args):
            "hbm_bytes_per_launch": round(fetch_b + write_b),
            "calibration": {"copy_mib": args.copy_mib, "fetch_kib_read": k_fetch, "fetch_factor": round(f_fetch, 4),
                            "write_kib_read": k_write, "write_factor": round(f_write, 4)}}
+    if args.l2:
+        hit = _counter(args.l2, "TCC_HIT_sum", args.kernel)[args.skip:]
+        miss = _counter(args.l2, "TCC_MISS_sum", args.kernel)[args.skip:]
+        if not hit or len(hit) != len(miss):
+            raise SystemExit("no matching TCC_HIT_sum / TCC_MISS_sum dispatches under %s" % args.l2)
+        res["l2_hit_rate"] = round(sum(hit) / max(sum(hit) + sum(miss), 1.0), 4)
+        res["l2_dispatches"] = len(hit)
     if args.json:
         res.update({"workload": args.workload, "storage": args.storage,
                     "kernel_source_hash": kernel_source_hash(args.name)})
@@ -138,6 +148,7 @@ def main():
         p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     p.add_argument("--kernel", required=True)
     p.add_argument("--skip", type=int, default=0)
+    p.add_argument("--l2", default=None)
     p.add_argument("--copy-mib", type=int, default=1024)
     p.add_argument("--json", default=None)
     p.add_argument("--name", default=None, choices=sorted(KERNEL_SOURCES))
