@@ -55,6 +55,9 @@ void launch_map_init(const MapDev& m, uint32_t num_buckets, int storage, hipStre
   init_refs_kernel<<<256, 256, 0, s>>>(m.tcache, (size_t)tile_refs_before(kCacheLevels) * m.tc_tiles);
   zero_words_kernel<<<16, 256, 0, s>>>(reinterpret_cast<uint4*>(m.tc_count), ((size_t)kCacheLevels * m.tc_tiles + 3) / 4);
   init_buckets_kernel<<<2048, 256, 0, s>>>(m.buckets, num_buckets);
+  // the flood-fill tile flags start at zero, and every mask computation
+  // leaves them so
+  zero_words_kernel<<<16, 256, 0, s>>>(reinterpret_cast<uint4*>(m.dirty), ((size_t)m.dirty_cap * 2 * 4 + 15) / 16);
   const size_t rec = (storage == RF_STORAGE_FP32) ? 8 : 4;
   zero_words_kernel<<<4096, 256, 0, s>>>(reinterpret_cast<uint4*>(m.sdfw), (size_t)m.max_blocks * 512 * rec / 16);
   zero_words_kernel<<<4096, 256, 0, s>>>(reinterpret_cast<uint4*>(m.rgb), (size_t)m.max_blocks * 512 * 4 / 16);

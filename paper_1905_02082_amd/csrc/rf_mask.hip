@@ -296,18 +296,10 @@ __global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta
     processed += n;
     if (processed > max_tiles_processed) {
       if (threadIdx.x == 0) atomicOr(&m.st->flags, (uint32_t)RF_FLAG_MASK_LIMIT);
+      __syncthreads();
+      for (int i = threadIdx.x; i < ntiles; i += blockDim.x) dirty[i] = 0;  // leave no flag behind
       break;
     }
-  }
-}
-
-__global__ void clear_dirty_kernel(Batch b) {
-  const int jb = batch_job(b, blockIdx.x);
-  const Job& J = b.job[jb];
-  const int i = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
-  if (i < J.tiles_x * J.tiles_y) {
-    J.m.dirty[i] = 0;
-    J.m.dirty[J.m.dirty_cap + i] = 0;
   }
 }
 
@@ -323,7 +315,6 @@ static int set_bases(Batch& b, int (*count)(const Job&)) {
 
 static int pixel_groups(const Job& J) { return (J.f.W * J.f.H + 255) / 256; }
 static int tile_count(const Job& J) { return J.tiles_x * J.tiles_y; }
-static int dirty_groups(const Job& J) { return (J.tiles_x * J.tiles_y + 255) / 256; }
 
 template <int DF, int STORAGE>
 static void mask_impl(Batch& b, const rf_mask_params& mp, hipStream_t s) {
@@ -339,8 +330,9 @@ static void mask_impl(Batch& b, const rf_mask_params& mp, hipStream_t s) {
   residual_kernel<DF, STORAGE><<<g, 256, 0, s>>>(b, mp.gamma);
   pixel_pass_kernel<<<g, 256, 0, s>>>(b, 0);
   if (eroded) pixel_pass_kernel<<<g, 256, 0, s>>>(b, 2);
-  g = set_bases(b, dirty_groups);
-  clear_dirty_kernel<<<g, 256, 0, s>>>(b);
+  // the tile flags are all zero here: map initialisation zeroes them, and
+  // every mask computation ends with both buffers empty (each parallel pass
+  // clears the flags it consumes, the finish drains the last buffer)
   g = set_bases(b, tile_count);
   for (int pass = 0; pass <= kFloodPasses; ++pass) flood_tiles_kernel<DF><<<g, 256, 0, s>>>(b, mp.theta, pass);
   flood_finish_kernel<DF><<<b.n, 1024, 0, s>>>(b, mp.theta, kFloodPasses & 1);
