@@ -84,17 +84,17 @@ struct Dda {
   }
 };
 
+// Capacity of a workgroup's list of first touches in LDS; first touches
+// beyond it go to the frame list directly.
+constexpr uint32_t kAllocList = 2048;
+
+// One thread's ray: its cells' blocks are inserted if absent and stamped with
+// the frame; the first touches are appended to the workgroup's list s_list
+// (s_n entries, LDS), or past its capacity to the frame list.
 template <int DF>
-__global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
-  // Per job: workgroups [0, carve_groups) take the carve segments of the
-  // carve-grid pixels, the rest the band segments of the other pixels, so the
-  // long rays share wavefronts with rays of similar length; the carve
-  // workgroups come first so that the longest chains start first.
-  const int jb = batch_job(b, blockIdx.x);
-  const Job& J = b.job[jb];
+__device__ __forceinline__ void alloc_ray(const Job& J, int g, uint32_t* s_list, uint32_t* s_n) {
   const MapDev& m = J.m;
   const FrameDev& f = J.f;
-  const int g = blockIdx.x - b.base[jb];
   int u, v;
   const int s_c = (int)m.carve_stride;
   if (g < J.carve_groups) {
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
     }
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) asm volatile("" : "+v"(old[q]));
-    // First touches are appended to the frame list with one counter atomic
+    // First touches are appended to the workgroup's list with one LDS atomic
     // per wavefront and batch (ballot + mbcnt give each its position).
     const int lane = threadIdx.x & 63;
     uint32_t tot = 0, off[kBatch];
@@ -195,16 +195,54 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
     }
     if (tot) {
       const int leader = __ffsll((long long)__ballot(true)) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&m.st->f_count, tot);
-      base = __builtin_amdgcn_readlane(base, leader);
+      uint32_t pos = 0;
+      if (lane == leader) pos = atomicAdd(s_n, tot);  // LDS
+      pos = __builtin_amdgcn_readlane(pos, leader);
+      // entries from position kAllocList on go to the frame list directly
+      const uint32_t lo = pos > kAllocList ? pos : kAllocList;
+      const uint32_t n_over = pos + tot > lo ? pos + tot - lo : 0u;
+      uint32_t gbase = 0;
+      if (n_over && lane == leader) gbase = atomicAdd(&m.st->f_count, n_over);
+      gbase = __builtin_amdgcn_readlane(gbase, leader);
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         if (!first[q]) continue;
-        const uint32_t i = base + off[q];
-        if (i < m.flist_cap) m.flist[i] = (uint32_t)hq[q];
+        const uint32_t i = pos + off[q];
+        if (i < kAllocList) {
+          s_list[i] = (uint32_t)hq[q];
+        } else {
+          const uint32_t k = gbase + (i - lo);
+          if (k < m.flist_cap) m.flist[k] = (uint32_t)hq[q];
+        }
       }
     }
+  }
+}
+
+template <int DF>
+__global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
+  // Per job: workgroups [0, carve_groups) take the carve segments of the
+  // carve-grid pixels, the rest the band segments of the other pixels, so the
+  // long rays share wavefronts with rays of similar length; the carve
+  // workgroups come first so that the longest chains start first.  A
+  // workgroup gathers its first touches in LDS and appends them to the frame
+  // list with one counter atomic at its end (one per wavefront and batch had
+  // made the counter's single address the bottleneck).
+  __shared__ uint32_t s_list[kAllocList];
+  __shared__ uint32_t s_n, s_base;
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  alloc_ray<DF>(J, blockIdx.x - b.base[jb], s_list, &s_n);
+  __syncthreads();
+  const uint32_t n = min(s_n, kAllocList);
+  if (threadIdx.x == 0) s_base = n ? atomicAdd(&m.st->f_count, n) : 0u;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t k = s_base + i;
+    if (k < m.flist_cap) m.flist[k] = s_list[i];
   }
 }
 
