@@ -1,7 +1,8 @@
 """Precision form: FP16 sdf/tau + u8 weight storage against FP32 storage and
 the FP64 oracle on the same seeded inputs (teacher-forced: every frame fused
-at its ground-truth pose).  The measured errors are printed and, when a
-gpurun_out/ folder exists, written to gpurun_out/precision.json."""
+at its ground-truth pose).  The measured errors are printed and, when the
+environment variable RF_RESULTS_DIR names a folder, written to
+precision.json there."""
 import json
 import os
 
@@ -41,9 +42,9 @@ def setup(rf):
 
 
 def record(key, value):
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    out = os.environ.get("RF_RESULTS_DIR", "")
     print("precision", key, value)
-    if os.path.isdir(out):
+    if out and os.path.isdir(out):
         path = os.path.join(out, "precision.json")
         d = json.load(open(path)) if os.path.exists(path) else {}
         d[key] = value
