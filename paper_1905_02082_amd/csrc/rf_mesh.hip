@@ -236,6 +236,12 @@ __global__ __launch_bounds__(kMeshThreads) void mesh_write_kernel(MapDev m, cons
                                                                   float* tris, uint32_t cap) {
   __shared__ int s_nb[8];
   __shared__ uint32_t s_wave[kMeshThreads / 64];
+  __shared__ uint32_t s_swave[kMeshThreads / 64];
+  // the block's cubes that emit triangles, compacted in thread order: cube,
+  // first output triangle, corner values
+  __shared__ uint16_t s_cube[kMeshThreads];
+  __shared__ uint32_t s_off[kMeshThreads];
+  __shared__ float s_f[kMeshThreads][8];
   const uint32_t n = min(m.st->n_blocks, m.max_blocks);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t base = scratch[groups + blockIdx.x];
@@ -256,20 +262,38 @@ __global__ __launch_bounds__(kMeshThreads) void mesh_write_kernel(MapDev m, cons
       const uint32_t y = __shfl_up(inc, o);
       if (lane >= o) inc += y;
     }
+    const unsigned long long sb = __ballot(cnt != 0u);
     if (lane == 63) s_wave[wave] = inc;
+    if (lane == 0) s_swave[wave] = (uint32_t)__popcll(sb);
     __syncthreads();
-    uint32_t before = 0, total = 0;
+    uint32_t before = 0, total = 0, sbefore = 0, stotal = 0;
 #pragma unroll
     for (int w = 0; w < kMeshThreads / 64; ++w) {
-      const uint32_t tw = s_wave[w];
+      const uint32_t tw = s_wave[w], sw = s_swave[w];
       before += w < wave ? tw : 0u;
       total += tw;
+      sbefore += w < wave ? sw : 0u;
+      stotal += sw;
     }
+    // The cubes that emit triangles are packed in thread order, so their
+    // triangles are written by consecutive threads at the same positions (a
+    // block has tens of such cubes, spread over all its wavefronts).
     if (cnt) {
-      const int l = threadIdx.x;
+      const uint32_t pos = sbefore + __builtin_amdgcn_mbcnt_hi((uint32_t)(sb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sb, 0u));
+      s_cube[pos] = (uint16_t)threadIdx.x;
+      s_off[pos] = base + before + inc - cnt;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s_f[pos][k] = f[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < stotal) {
+      const int l = s_cube[threadIdx.x];
       const int v[3] = {8 * bx + (l & 7), 8 * by + ((l >> 3) & 7), 8 * bz + (l >> 6)};
-      MeshOut out{tris, cap, base + before + inc - cnt};
-      cube_write(f, v, s, out);
+      float fc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) fc[k] = s_f[threadIdx.x][k];
+      MeshOut out{tris, cap, s_off[threadIdx.x]};
+      cube_write(fc, v, s, out);
     }
     base += total;
   }
