@@ -239,8 +239,9 @@ rf_status raycast_depth(rf_map* m, const rf_frame* f, const double* d_pose, floa
  * the stream. */
 rf_status map_status(rf_map* m, void* stream, uint32_t* flags, uint32_t* n_blocks);
 
-/* The blocks listed by the last hashmap_allocate: d_keys (device int32,
- * cap x 3 block coordinates); *d_count (device uint32) = list length. */
+/* The blocks listed by the last hashmap_allocate (each once, in an order that
+ * varies from run to run): d_keys (device int32, cap x 3 block coordinates);
+ * *d_count (device uint32) = list length. */
 rf_status hashmap_frame_blocks(rf_map* m, int32_t* d_keys, uint32_t cap, uint32_t* d_count, void* stream);
 
 /* Export of every allocated block (checkpoint): d_keys int32 cap x 3,
