@@ -342,6 +342,25 @@ def test_full_size_static_room_teacher_forced(rf, static_seq):
         assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
 
 
+def test_full_size_large_rooms_allocation(rf):
+    """640x480 at 0.5 cm voxels, first frame (every block new), carve stride
+    2: carve workgroups touch up to ~3900 distinct blocks each, more than a
+    workgroup's LDS list of first touches holds, so the path that appends
+    the excess to the frame list directly runs too."""
+    seq = synth.large_rooms(n_frames=2)
+    m = rf.Map(map_params(rf, seq, max_blocks=1 << 19))
+    o32 = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=32)
+    for k in range(2):
+        g = gpu_frame(rf, seq, k)
+        m.allocate(g, dev_pose(seq.poses[k]))
+        F_gpu = gpu_keyset(m.frame_blocks())
+        F_orc = o32.allocate(orc_frame(seq, k), seq.poses[k])
+        assert len(F_orc) > 50000
+        assert np.array_equal(F_gpu, F_orc), k
+    flags, nb = m.status()
+    assert flags == 0 and nb == o32.num_blocks
+
+
 def test_track_is_deterministic(rf, room):
     """Order-independent fixed-point reduction: repeated runs are bit-identical."""
     m, _, _ = integrate_teacher_forced(rf, room, range(2))
