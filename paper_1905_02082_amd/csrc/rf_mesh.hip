@@ -189,24 +189,36 @@ __device__ __forceinline__ void neighbour_slots(const MapDev& m, uint32_t b, int
   if (t < 8) s_nb[t] = t == 0 ? (int)b : find_slot(m, bx + (t & 1), by + ((t >> 1) & 1), bz + (t >> 2));
 }
 
+// The same for block b if b < n (the walks look one block ahead: the next
+// block's hash probes run while the current block's corner records load).
+__device__ __forceinline__ void prefetch_slots(const MapDev& m, uint32_t b, uint32_t n, int* s_nb) {
+  if (b < n && threadIdx.x < 8) {
+    int bx, by, bz;
+    unpack_key(m.block_keys[b], bx, by, bz);
+    neighbour_slots(m, b, bx, by, bz, s_nb);
+  }
+}
+
 // Pass 1: triangles per workgroup -> scratch[g].
 template <int STORAGE>
 __global__ __launch_bounds__(kMeshThreads) void mesh_count_kernel(MapDev m, uint32_t* scratch) {
-  __shared__ int s_nb[8];
+  __shared__ int s_nb[2][8];
   __shared__ uint32_t s_sum;
   if (threadIdx.x == 0) s_sum = 0u;
-  __syncthreads();
   const uint32_t n = min(m.st->n_blocks, m.max_blocks);
+  prefetch_slots(m, blockIdx.x, n, s_nb[0]);
   uint32_t mine = 0;
-  for (uint32_t b = blockIdx.x; b < n; b += gridDim.x) {
-    int bx, by, bz;
-    unpack_key(m.block_keys[b], bx, by, bz);
-    __syncthreads();  // the previous block's s_nb is no longer read
-    neighbour_slots(m, b, bx, by, bz, s_nb);
+  int cur = 0;
+  for (uint32_t b = blockIdx.x; b < n; b += gridDim.x, cur ^= 1) {
+    // this block's slots are complete, the buffer the next block's go to is
+    // no longer read
     __syncthreads();
     float f[8];
-    if (cube_corners<STORAGE>(m, s_nb, threadIdx.x, f)) mine += (uint32_t)cube_count(f);
+    const bool ok = cube_corners<STORAGE>(m, s_nb[cur], threadIdx.x, f);
+    prefetch_slots(m, b + gridDim.x, n, s_nb[cur ^ 1]);
+    if (ok) mine += (uint32_t)cube_count(f);
   }
+  __syncthreads();
   atomicAdd(&s_sum, mine);
   __syncthreads();
   if (threadIdx.x == 0) scratch[blockIdx.x] = s_sum;
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(1024) void mesh_scan_kernel(uint32_t* scratch, int 
 template <int STORAGE>
 __global__ __launch_bounds__(kMeshThreads) void mesh_write_kernel(MapDev m, const uint32_t* scratch, int groups,
                                                                   float* tris, uint32_t cap) {
-  __shared__ int s_nb[8];
+  __shared__ int s_nb[2][8];
   __shared__ uint32_t s_wave[kMeshThreads / 64];
   __shared__ uint32_t s_swave[kMeshThreads / 64];
   // the block's cubes that emit triangles, compacted in thread order: cube,
@@ -246,14 +258,17 @@ __global__ __launch_bounds__(kMeshThreads) void mesh_write_kernel(MapDev m, cons
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t base = scratch[groups + blockIdx.x];
   const float s = m.s;
-  for (uint32_t b = blockIdx.x; b < n; b += gridDim.x) {
+  prefetch_slots(m, blockIdx.x, n, s_nb[0]);
+  int cur = 0;
+  for (uint32_t b = blockIdx.x; b < n; b += gridDim.x, cur ^= 1) {
     int bx, by, bz;
     unpack_key(m.block_keys[b], bx, by, bz);
-    __syncthreads();
-    neighbour_slots(m, b, bx, by, bz, s_nb);
+    // this block's slots are complete; the previous block's LDS lists and
+    // the buffer the next block's slots go to are no longer read
     __syncthreads();
     float f[8];
-    const bool ok = cube_corners<STORAGE>(m, s_nb, threadIdx.x, f);
+    const bool ok = cube_corners<STORAGE>(m, s_nb[cur], threadIdx.x, f);
+    prefetch_slots(m, b + gridDim.x, n, s_nb[cur ^ 1]);
     const uint32_t cnt = ok ? (uint32_t)cube_count(f) : 0u;
     // exclusive prefix over the workgroup in thread order
     uint32_t inc = cnt;
