@@ -4,12 +4,14 @@
 // Allocation: one thread per pixel walks the block grid along its band (or
 // carve) segment with a DDA; each visited block is inserted into the hash by
 // CAS and, the first time it is touched in this frame (per-bucket frame
-// stamp, exchanged atomically), appended to the frame's block list.  Carve
-// rays run in workgroups of their own; cells are probed 8 at a time, with
-// their bucket loads, stamp exchanges and list appends each issued together.
+// stamp, exchanged atomically), appended to the frame's block list (through
+// a per-workgroup list in LDS).  Carve rays run in workgroups of their own;
+// cells are probed 12 at a time, with their bucket loads, stamp exchanges and
+// list appends each issued together.
 //
 // Integration: workgroups stride over the listed blocks, 256 threads x 2
-// voxels per block, two blocks per step; only voxels the frame updates are
+// voxels per block, two blocks per step, the next step's list entries and
+// buckets fetched during the current one; only voxels the frame updates are
 // written.  Records are SoA per block, so a workgroup's loads and stores are
 // contiguous 4-KiB (FP32) / 2-KiB (FP16) runs.
 #include "rf_device.h"
