@@ -28,11 +28,14 @@
 //    6x6 Cholesky in FP64; pyramid level l takes every 2^l-th pixel.
 //  * allocation: band segment z in [max(D-tau,0), D+tau] for every valid
 //    unmasked pixel, carve segment z in [0, D+tau] on a carve_stride pixel grid;
-//    a block-grid DDA visits the cells of each segment.
+//    a block-grid DDA visits the cells of each segment.  A measurement beyond
+//    depth_max (the clipping plane) is not valid for registration, the mask or
+//    the band, but its carve segment z in [0, depth_max] is walked.
 //  * integration: nearest-pixel projection, eta = D - z (optical axis), band
-//    |eta| <= tau -> d = eta (and colour), eta > tau and z <= depth_max ->
-//    d = tau (free space), eta < -tau -> untouched; observation weight 1,
-//    weight cap max_weight; colour rounded half-to-even.
+//    |eta| <= tau and D <= depth_max -> d = eta (and colour), eta > tau and
+//    z <= depth_max -> d = tau (free space, also in front of measurements
+//    beyond depth_max), otherwise untouched; observation weight 1, weight cap
+//    max_weight; colour rounded half-to-even.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -171,10 +174,9 @@ inline bool depth_valid(float D, float dmax) { return D > 0.0f && D <= dmax; }
 
 template <class Real>
 inline Real luminance(const uint8_t* c) {
-  // ((0.2126 R + 0.7152 G) + 0.0722 B) / 255; the FP32 mirror scales by the
-  // FP32 reciprocal of 255, as the kernels do, the reference divides exactly
+  // ((0.2126 R + 0.7152 G) + 0.0722 B) / 255 (Sec. III-B: intensity of the
+  // RGB colour, scaled to [0, 1]); a correctly rounded division in Real
   const Real x = (Real)0.2126f*(Real)c[0] + (Real)0.7152f*(Real)c[1] + (Real)0.0722f*(Real)c[2];
-  if (std::is_same<Real, float>::value) return x * (Real)(1.0f / 255.0f);
   return x / (Real)255.0f;
 }
 
@@ -482,11 +484,16 @@ void allocate(MapBase& m, const Frame& f, const double* T, const uint8_t* mask) 
   for (int v = 0; v < f.H; ++v)
     for (int u = 0; u < f.W; ++u) {
       float D = depth_at(f, u, v);
-      if (!depth_valid(D, P.depth_max)) continue;
+      if (!(D > 0.0f)) continue;  // no measurement
       if (mask && mask[(size_t)v*f.W + u]) continue;
       bool carve = (u % P.carve_stride == 0) && (v % P.carve_stride == 0);
+      // a measurement beyond depth_max is too far to be integrated but still
+      // shows free space up to the clipping plane (Sec. III-D): only its carve
+      // segment is walked, and it ends at the clipping plane
+      bool far = !(D <= P.depth_max);
+      if (far && !carve) continue;
       float zn = carve ? 0.0f : std::max(D - tau, 0.0f);
-      float zf = D + tau;
+      float zf = far ? P.depth_max : D + tau;
       float rx = ((float)u - f.cx)*ifx, ry = ((float)v - f.cy)*ify;
       float X0[3] = {rx*zn, ry*zn, zn}, X1[3] = {rx*zf, ry*zf, zf};
       float P0[3], P1[3];
@@ -531,11 +538,14 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
       if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) continue;
       int u = (int)ur, v = (int)vr;
       float D = depth_at(f, u, v);
-      if (!depth_valid(D, P.depth_max)) continue;
+      if (!(D > 0.0f)) continue;  // no measurement
       if (mask && mask[(size_t)v*f.W + u]) continue;
       float eta = D - X[2];
       if (eta < -tau) continue;
       bool band = (eta <= tau);
+      // the band of a measurement beyond depth_max is not integrated; the free
+      // space in front of it is carved like any other (Sec. III-D)
+      if (band && !(D <= P.depth_max)) continue;
       if (!band && !(X[2] <= zclip)) continue;
       // --- value path in Real
       Real dval;
@@ -938,7 +948,7 @@ int orc_track(void* p, const orc_frame* fr, double* T, const uint8_t* mask, int 
 }
 
 // Levenberg-Marquardt variant of the same coarse-to-fine registration (the
-// solver Section III-B names), in the order the GPU schedule evaluates it:
+// solver Section III-B names), as a fixed budget of cost evaluations:
 // evaluation e (e = 0 .. levels*iters - 1, level by level) computes the normal
 // equations at the candidate pose C_e.  The first evaluation of each level is
 // accepted as it is (its cost is not comparable with the previous level's);
