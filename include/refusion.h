@@ -59,6 +59,8 @@ typedef int32_t rf_status;
 #define RF_FLAG_TRACK_FEW_PIXELS 0x4u /* fewer than min_valid residuals: pass stopped, pose kept */
 #define RF_FLAG_TRACK_SINGULAR 0x8u   /* Cholesky pivot <= 1e-12 trace(H): pass stopped, pose kept */
 #define RF_FLAG_MASK_LIMIT 0x10u      /* flood-fill work limit reached (never expected) */
+#define RF_FLAG_TRACK_RANGE 0x20u     /* a workgroup's normal-equation term was non-finite or |term| >= 2^34
+                                         (beyond the fixed-point totals): pass stopped, pose kept */
 
 #define RF_DEPTH_U16 0
 #define RF_DEPTH_F32 1

@@ -17,7 +17,7 @@ import torch
 
 from . import _native as N
 from ._native import (RF_DEPTH_F32, RF_DEPTH_U16, RF_FLAG_HASH_FULL, RF_FLAG_MASK_LIMIT,  # noqa: F401
-                      RF_FLAG_POOL_FULL, RF_FLAG_TRACK_FEW_PIXELS, RF_FLAG_TRACK_SINGULAR,
+                      RF_FLAG_POOL_FULL, RF_FLAG_TRACK_FEW_PIXELS, RF_FLAG_TRACK_RANGE, RF_FLAG_TRACK_SINGULAR,
                       RF_STORAGE_FP16_U8, RF_STORAGE_FP32)
 
 __all__ = ["MapParams", "TrackParams", "MaskParams", "Frame", "Map", "Session", "Pipeline", "process_batch",

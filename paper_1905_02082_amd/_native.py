@@ -17,6 +17,7 @@ RF_FLAG_HASH_FULL = 0x2
 RF_FLAG_TRACK_FEW_PIXELS = 0x4
 RF_FLAG_TRACK_SINGULAR = 0x8
 RF_FLAG_MASK_LIMIT = 0x10
+RF_FLAG_TRACK_RANGE = 0x20
 RF_DEPTH_U16, RF_DEPTH_F32 = 0, 1
 RF_STORAGE_FP32, RF_STORAGE_FP16_U8 = 0, 1
 

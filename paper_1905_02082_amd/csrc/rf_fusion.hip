@@ -116,13 +116,18 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g, uint32_t* s_list,
   const uint32_t frame_id = m.st->epoch;
   const int idx = v * f.W + u;
   const float D = load_depth<DF>(f, idx);
-  if (!depth_ok(D, m.dmax)) return;
+  if (!(D > 0.0f)) return;  // no measurement
   if (mask && mask[idx]) return;
+  const bool carve = (u % s_c == 0) && (v % s_c == 0);
+  // A measurement beyond depth_max (the clipping plane) is too far to be
+  // integrated but still shows free space up to the plane (Sec. III-D): only
+  // its carve segment is walked, and it ends at the clipping plane.
+  const bool far = !(D <= m.dmax);
+  if (far && !carve) return;
   float R[9], t[3];
   load_pose_f(pose, R, t);
-  const bool carve = (u % s_c == 0) && (v % s_c == 0);
   const float zn = carve ? 0.0f : fmaxf(D - m.tau, 0.0f);
-  const float zf = D + m.tau;
+  const float zf = far ? m.dmax : D + m.tau;
   const float rx = ((float)u - f.cx) * f.ifx, ry = ((float)v - f.cy) * f.ify;
   const float X0[3] = {rx * zn, ry * zn, zn}, X1[3] = {rx * zf, ry * zf, zf};
   float P0[3], P1[3];
@@ -368,10 +373,16 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       band[v] = false;
-      if (!vis[v] || !depth_ok(D[v], m.dmax) || (mask && mk[v])) continue;
+      if (!vis[v] || !(D[v] > 0.0f) || (mask && mk[v])) continue;
       const float eta = D[v] - X2[v];
       if (eta < -m.tau) continue;
       band[v] = (eta <= m.tau);
+      // the band of a measurement beyond depth_max is not integrated; the
+      // free space in front of it is carved like any other (Sec. III-D)
+      if (band[v] && !(D[v] <= m.dmax)) {
+        band[v] = false;
+        continue;
+      }
       if (!band[v] && !(X2[v] <= m.dmax)) continue;
       const float dval = band[v] ? eta : m.tau;
       VoxelStore<STORAGE>::store(m, vidx[v], (W[v] * sdf[v] + dval) / (W[v] + 1.0f),

@@ -53,12 +53,14 @@ struct TrackArgs {
 __device__ __forceinline__ unsigned long long* acc_buf(const MapDev& m, int b) {
   return reinterpret_cast<unsigned long long*>(m.partials) + (size_t)b * kBufWords;
 }
-// The words an accumulator buffer actually uses: three chunks per term per
-// copy (the rest of each 128-byte line is padding against false sharing).
-constexpr int kUsedWords = kAccCopies * kNE * 3;
+// The words an accumulator buffer actually uses: three chunks and a range
+// marker per term per copy (the rest of each 128-byte line is padding against
+// false sharing).
+constexpr int kUsedPerTerm = 4;
+constexpr int kUsedWords = kAccCopies * kNE * kUsedPerTerm;
 __device__ __forceinline__ unsigned long long* used_word(unsigned long long* buf, int q) {
-  const int copy = q / (kNE * 3), r = q % (kNE * 3);
-  return buf + copy * kCopyWords + (r / 3) * kTermWords + (r % 3);
+  const int copy = q / (kNE * kUsedPerTerm), r = q % (kNE * kUsedPerTerm);
+  return buf + copy * kCopyWords + (r / kUsedPerTerm) * kTermWords + (r % kUsedPerTerm);
 }
 __device__ __forceinline__ double* pose_buf(const MapDev& m, double* user, int b) {
   return b == 2 ? user : reinterpret_cast<double*>(m.partials) + (size_t)3 * kBufWords + 16 * b;
@@ -72,9 +74,16 @@ __device__ __forceinline__ double* lm_state(const MapDev& m, int b) {
 
 // Adds v to a term: v 2^60 truncated toward zero as a 96-bit two's
 // complement integer c0 + c1 2^32 + c2 2^64 (c0, c1 unsigned 32-bit, c2 signed).
-__device__ __forceinline__ void fixed_add(unsigned long long* acc, double v) {
+// A non-finite v, or |v| >= 2^34 (beyond the range the totals can hold), is
+// not added: the term's range marker acc[3] is set instead, and its total
+// then reads as NaN, which stops the registration pass (RF_FLAG_TRACK_RANGE).
+// Returns false in that case.
+__device__ __forceinline__ bool fixed_add(unsigned long long* acc, double v) {
   double a = fabs(v) * kFixScale;
-  if (!(a < 0x1p94)) a = 0.0;  // non-finite or out of range: contributes nothing
+  if (!(a < 0x1p94)) {
+    atomicOr(&acc[3], 1ull);
+    return false;
+  }
   const double hi_d = floor(a * 0x1p-64);
   unsigned long long hi = (unsigned long long)hi_d;
   unsigned long long lo = (unsigned long long)(a - hi_d * 0x1p64);
@@ -86,18 +95,22 @@ __device__ __forceinline__ void fixed_add(unsigned long long* acc, double v) {
   if (c0) atomicAdd(&acc[0], c0);
   if (c1) atomicAdd(&acc[1], c1);
   if (c2) atomicAdd(&acc[2], c2);
+  return true;
 }
 
 // Total of a term over the accumulator copies as FP64 (exact integer sums and
 // 128-bit combination, one final rounding).
+// A term whose range marker is set in any copy totals NaN.
 __device__ __forceinline__ double fixed_total(const unsigned long long* acc) {
-  unsigned long long s0 = 0, s1 = 0, s2 = 0;
+  unsigned long long s0 = 0, s1 = 0, s2 = 0, bad = 0;
 #pragma unroll
   for (int c = 0; c < kAccCopies; ++c) {
     s0 += acc[c * kCopyWords];
     s1 += acc[c * kCopyWords + 1];
     s2 += acc[c * kCopyWords + 2];
+    bad |= acc[c * kCopyWords + 3];
   }
+  if (bad) return __longlong_as_double(0x7FF8000000000000ll);
   unsigned long long lo = s0 + (s1 << 32);
   unsigned long long hi = s2 + (s1 >> 32) + (lo < s0 ? 1ull : 0ull);
   const bool neg = (long long)hi < 0;
@@ -133,7 +146,11 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
                                   int* s_state) {
   const int lane = threadIdx.x;
   int state = 0;
-  if (s_ne[28] < (double)a.min_valid) state = RF_FLAG_TRACK_FEW_PIXELS;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < kNE; ++k) finite &= (s_ne[k] == s_ne[k]);
+  if (!finite) state = RF_FLAG_TRACK_RANGE;
+  else if (s_ne[28] < (double)a.min_valid) state = RF_FLAG_TRACK_FEW_PIXELS;
   double tr = 0.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) tr += s_ne[tri_index(i, i)];
@@ -706,7 +723,10 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     double tot = 0.0;
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) tot += s_g[threadIdx.x][g];
-    fixed_add(acc_buf(m, a.acc_write) + (g0 % kAccCopies) * kCopyWords + threadIdx.x * kTermWords, tot);
+    if (!fixed_add(acc_buf(m, a.acc_write) + (g0 % kAccCopies) * kCopyWords + threadIdx.x * kTermWords, tot)) {
+      atomicOr(&m.st->flags, (uint32_t)RF_FLAG_TRACK_RANGE);
+      if (stats) atomicOr(&stats->flags, (uint32_t)RF_FLAG_TRACK_RANGE);
+    }
   }
 }
 

@@ -107,8 +107,20 @@ class _Live:
 
 
 def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget: int, max_batch=64, depth=2,
-          dynamic=True, device="cuda", pinned_frames=None, progress=None) -> ServeResult:
-    """Runs all sessions to completion; returns latency and throughput."""
+          dynamic=True, device="cuda", pinned_frames=None, progress=None, on_finish=None) -> ServeResult:
+    """Runs all sessions to completion; returns latency and throughput.
+
+    on_finish(spec, session), if given, is called once per session after its
+    last frame has completed and before its map is released (the session's
+    pose and map are final then).  A session whose map alone exceeds
+    hbm_budget could never be admitted: it raises ValueError up front."""
+    for spec in specs:
+        nb = hashmap_bytes(spec.params)
+        if nb > hbm_budget:
+            raise ValueError("session %r needs %d bytes of map arena, more than the whole HBM budget (%d)"
+                             % (spec.sid, nb, hbm_budget))
+        if len(spec.arrivals) == 0 or len(spec.order) != len(spec.arrivals):
+            raise ValueError("session %r: order and arrivals must be non-empty and of equal length" % spec.sid)
     dev = torch.device(device)
     stream = torch.cuda.current_stream(dev)
     if pinned_frames is None:
@@ -214,6 +226,8 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
         retire(block=False)
         # release finished sessions
         for lv in [lv for lv in live if lv.done == len(lv.spec.arrivals)]:
+            if on_finish is not None:
+                on_finish(lv.spec, lv.session)
             live.remove(lv)
             used -= lv.nbytes
             del lv.session

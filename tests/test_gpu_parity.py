@@ -37,10 +37,10 @@ def dyn_small():
     return synth.dynamic_room(n_frames=24, width=160, height=120, n_clusters=2, movers="in_view")
 
 
-def integrate_teacher_forced(rf, seq, frames, storage="fp32", orc_storage=0, masks=None):
+def integrate_teacher_forced(rf, seq, frames, storage="fp32", orc_storage=0, masks=None, max_blocks=None):
     """Integrates the given frames at ground-truth poses on the GPU and both
     oracle maps; returns (gpu map, fp64 oracle, fp32 mirror)."""
-    m = rf.Map(map_params(rf, seq, storage))
+    m = rf.Map(map_params(rf, seq, storage, max_blocks=max_blocks))
     o64, o32 = oracle_maps(seq, orc_storage)
     for i, k in enumerate(frames):
         mk = None if masks is None else masks[i]
@@ -115,6 +115,38 @@ def test_integration_masked_pixels_untouched(rf, room):
     masks = [None, mask, (rng.uniform(size=mask.shape) < 0.3).astype(np.uint8)]
     m, o64, o32 = integrate_teacher_forced(rf, room, range(3), masks=masks)
     assert_maps_match(m, o64, o32)
+
+
+@pytest.mark.parametrize("storage,orc_storage", [("fp32", 0), ("fp16", 1)])
+def test_far_measurements_carve_up_to_clipping_plane(rf, room, storage, orc_storage):
+    """Clipping plane at 1.2 m in the 2 m room: most measurements lie beyond
+    it; they add no band but carve free space in front of the plane along
+    their carve rays (Sec. III-D).  Block sets and voxels bit-exact against
+    the mirror, and the far pixels really carve (more free updates than with
+    those pixels removed from the frame)."""
+    import dataclasses
+    near = dataclasses.replace(room, depth_max=1.2)
+    d0 = synth.depth_metres(near, 0)
+    assert (d0 > 1.2).mean() > 0.5
+    m, o64, o32 = integrate_teacher_forced(rf, near, range(3), storage=storage, orc_storage=orc_storage)
+    gk, gs, gw, gc = gpu_export_sorted(m)
+    k32, s32, w32, c32 = o32.export()
+    assert np.array_equal(gk, k32)
+    np.testing.assert_array_equal(gs, s32.astype(np.float32))
+    np.testing.assert_array_equal(gw, w32.astype(np.float32))
+    np.testing.assert_array_equal(gc, c32)
+    # the same frame with its far pixels cleared carves less
+    cut = dataclasses.replace(near, depth=near.depth.copy())
+    for k in range(near.n):
+        cut.depth[k][synth.depth_metres(near, k) > 1.2] = 0
+    m2 = rf.Map(map_params(rf, cut, storage))
+    for k in range(3):
+        g = gpu_frame(rf, cut, k)
+        P = dev_pose(cut.poses[k])
+        m2.allocate(g, P)
+        m2.integrate(g, P)
+    torch.cuda.synchronize()
+    assert m2.status()[1] < m.status()[1]
 
 
 def test_integration_fp16_storage_matches_mirror(rf, room):
@@ -342,6 +374,124 @@ def test_full_size_static_room_teacher_forced(rf, static_seq):
         assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
 
 
+@pytest.fixture(scope="module")
+def dyn_full():
+    """640x480 dynamic room, movers in view from frame 0 (13 frames)."""
+    return synth.dynamic_room(n_frames=13, movers="in_view")
+
+
+@pytest.fixture(scope="module")
+def dyn_full_maps(rf, dyn_full):
+    """The dynamic room fused at ground-truth poses with ground-truth masks
+    (frames 0, 3, 6, 9), on the GPU and both oracle maps."""
+    seq = dyn_full
+    ks = list(range(0, 12, 3))
+    masks = [(seq.labels[k] > 0).astype(np.uint8) for k in ks]
+    m = rf.Map(map_params(rf, seq, max_blocks=1 << 17))
+    o64, o32 = oracle_maps(seq)
+    for k, mk in zip(ks, masks):
+        g = gpu_frame(rf, seq, k)
+        P = dev_pose(seq.poses[k])
+        mt = torch.from_numpy(mk).cuda()
+        m.allocate(g, P, mt)
+        m.integrate(g, P, mt)
+        for o in (o64, o32):
+            o.allocate(orc_frame(seq, k), seq.poses[k], mk)
+            o.integrate(orc_frame(seq, k), seq.poses[k], mk)
+    torch.cuda.synchronize()
+    return m, o64, o32
+
+
+def test_full_size_dynamic_room_mask_stages(rf, dyn_full, dyn_full_maps):
+    """640x480 frame with movers in view: residual, raw, eroded, flood-filled
+    and final masks bit-exact against the FP32 mirror, on non-trivial content
+    (the fill grows the eroded seeds across many 32x32 tiles)."""
+    seq = dyn_full
+    m, _, o32 = dyn_full_maps
+    assert_maps_match(m, dyn_full_maps[1], o32)
+    k = 12
+    g = gpu_frame(rf, seq, k)
+    res = torch.empty((seq.height, seq.width), dtype=torch.float32, device="cuda")
+    out = m.dynamic_mask(g, dev_pose(seq.poses[k]), rf.MaskParams(0.5, 0.007), residual=res, stages=True)
+    ref = o32.mask(orc_frame(seq, k), seq.poses[k], 0.5, 0.007)
+    np.testing.assert_array_equal(res.cpu().numpy(), ref["residual"])
+    for key in ("raw", "eroded", "filled", "final"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+    assert ref["eroded"].sum() > 1000 and ref["filled"].sum() > 2 * ref["eroded"].sum()
+    filled_tiles = {(v // 32, u // 32) for v, u in zip(*np.nonzero(ref["filled"]))}
+    assert len(filled_tiles) > 30
+
+
+def test_full_size_dynamic_room_three_level_poses(rf, dyn_full, dyn_full_maps):
+    """Both registration passes of a 640x480 dynamic frame, 3 levels x 10
+    iterations, against the FP64 oracle from the same start: pass 1 without a
+    mask, pass 2 with the mask the FP32 mirror computes at the FP64 pass-1
+    pose; within 1e-4 m / 1e-5 rad."""
+    seq = dyn_full
+    m, o64, o32 = dyn_full_maps
+    k = 12
+    tp = rf.TrackParams(seq.levels, seq.iters)
+    g, fr = gpu_frame(rf, seq, k), orc_frame(seq, k)
+    T0 = seq.poses[k - 3]
+    P = dev_pose(T0)
+    m.track(g, P, tp)
+    T1, fl, _ = o64.track(fr, T0, seq.levels, seq.iters)
+    assert fl == 0
+    dt, dr = pose_error(P.cpu().numpy(), T1)
+    assert dt <= 1e-4 and dr <= 1e-5, (dt, dr)
+    M = o32.mask(fr, T1, 0.5, 0.007)["final"]
+    assert M.sum() > 10000
+    P = dev_pose(T1)
+    m.track(g, P, tp, torch.from_numpy(M).cuda())
+    T2, fl, _ = o64.track(fr, T1, seq.levels, seq.iters, mask=M)
+    assert fl == 0
+    dt, dr = pose_error(P.cpu().numpy(), T2)
+    assert dt <= 1e-4 and dr <= 1e-5, (dt, dr)
+
+
+def test_full_size_static_room_three_level_pose(rf, static_seq):
+    """640x480 static room, registration of frame 3 from frame 2's pose with
+    3 levels x 10 iterations on a map of frames 0-2: within 1e-4 m / 1e-5 rad
+    of the FP64 oracle."""
+    seq = static_seq
+    m = rf.Map(map_params(rf, seq, max_blocks=1 << 17))
+    o64 = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=64)
+    for k in range(3):
+        g = gpu_frame(rf, seq, k)
+        P = dev_pose(seq.poses[k])
+        m.allocate(g, P)
+        m.integrate(g, P)
+        o64.allocate(orc_frame(seq, k), seq.poses[k])
+        o64.integrate(orc_frame(seq, k), seq.poses[k])
+    P = dev_pose(seq.poses[2])
+    m.track(gpu_frame(rf, seq, 3), P, rf.TrackParams(seq.levels, seq.iters))
+    T, fl, _ = o64.track(orc_frame(seq, 3), seq.poses[2], seq.levels, seq.iters)
+    assert fl == 0
+    dt, dr = pose_error(P.cpu().numpy(), T)
+    assert dt <= 1e-4 and dr <= 1e-5, (dt, dr)
+    assert pose_error(T, seq.poses[3])[0] < 5e-3
+
+
+@pytest.mark.parametrize("storage,orc_storage", [("fp32", 0), ("fp16", 1)])
+def test_full_size_large_rooms_integration(rf, storage, orc_storage):
+    """The 0.5 cm-voxel large rooms, two 640x480 frames fused at ground-truth
+    poses (~65 k blocks per frame, measurements beyond the clipping plane
+    carving in front of it): voxels bit-exact against the FP32 (FP16) mirror
+    and the FP32 sdf within 1e-5 m of FP64."""
+    seq = synth.large_rooms(n_frames=2)
+    m, o64, om = integrate_teacher_forced(rf, seq, range(2), storage=storage, orc_storage=orc_storage,
+                                          max_blocks=1 << 18)
+    gk, gs, gw, gc = gpu_export_sorted(m)
+    km, sm, wm, cm = om.export()
+    assert np.array_equal(gk, km) and len(gk) > 50000
+    np.testing.assert_array_equal(gs, sm.astype(np.float32))
+    np.testing.assert_array_equal(gw, wm.astype(np.float32))
+    np.testing.assert_array_equal(gc, cm)
+    k64, s64, w64, _ = o64.export()
+    err = np.abs(gs.astype(np.float64) - s64)[w64 > 0]
+    assert err.max() <= (1e-5 if storage == "fp32" else 2 * seq.truncation * 2.0 ** -12)
+
+
 def test_full_size_large_rooms_allocation(rf):
     """640x480 at 0.5 cm voxels, first frame (every block new), carve stride
     2: carve workgroups touch up to ~3900 distinct blocks each, more than a
@@ -399,3 +549,32 @@ def test_track_singular_plane_keeps_pose(rf):
     iters, fl = track_stats(stats)
     assert fl & rf.RF_FLAG_TRACK_SINGULAR and iters == 0
     np.testing.assert_array_equal(P.cpu().numpy(), T0)
+
+
+def test_track_out_of_range_terms_stop_the_pass(rf, room):
+    """The parity room moved 60 km along x: the rotational Jacobian y x grad S
+    reaches ~6e4 per pixel, so a tile's normal-equation sums exceed the 2^34
+    range of the fixed-point totals.  Those terms are not dropped silently:
+    the pass stops with RF_FLAG_TRACK_RANGE and keeps the pose.  The same
+    scene at the origin registers without the flag."""
+    far = np.eye(4)
+    far[0, 3] = 6.0e4
+    res = {}
+    for name, off in (("origin", np.eye(4)), ("far", far)):
+        m = rf.Map(map_params(rf, room))
+        for k in range(2):
+            g = gpu_frame(rf, room, k)
+            P = dev_pose(off @ room.poses[k])
+            m.allocate(g, P)
+            m.integrate(g, P)
+        T0 = off @ room.poses[1]
+        P = dev_pose(T0)
+        stats = torch.zeros(16, dtype=torch.float64, device="cuda")
+        m.track(gpu_frame(rf, room, 2), P, rf.TrackParams(room.levels, room.iters), None, stats)
+        iters, fl = track_stats(stats)
+        res[name] = (iters, fl, P.cpu().numpy(), T0, m.status()[0])
+    iters, fl, T, T0, mflags = res["origin"]
+    assert fl == 0 and iters > 0 and not np.array_equal(T, T0)
+    iters, fl, T, T0, mflags = res["far"]
+    assert fl & rf.RF_FLAG_TRACK_RANGE and mflags & rf.RF_FLAG_TRACK_RANGE
+    np.testing.assert_array_equal(T, T0)
