@@ -1,30 +1,40 @@
 #!/usr/bin/env python3
 """Throughput of the ReFusion per-frame hot path on one MI355X.
 
-Workload (default): the 640x480 static indoor room -- 300 frames of uint16
-millimetre depth (0.3-5 m) + RGB8, ray-cast from a seeded 4x4x3 m room with
-20 textured boxes/spheres, Kinect-like axial noise and 2% dropout; voxel 1 cm,
-truncation 3 cm, 8^3 blocks, 2^20 buckets, 3-level pyramid x 10 Gauss-Newton
-iterations, Table I weights (w_c 0.025, theta 0.007, gamma 0.5).
+Headline workload (default): the large rooms -- a 10x10x3 m multi-room
+layout with 150 textured primitives, 1000 frames of 640x480 uint16
+millimetre depth (0.3-5 m) + RGB8 with Kinect-like axial noise and 2%
+dropout; voxel 0.5 cm, truncation 3 cm, 8^3 blocks, 2^22 buckets, clipping
+plane 3.5 m (measurements beyond it carve free space up to it), 3-level
+pyramid x 10 Gauss-Newton iterations, Table I weights (w_c 0.025, theta
+0.007, gamma 0.5), FP32 storage.
 
 One step = one frame through the whole method: registration without mask,
 residual mask with flood fill, registration with the mask, block allocation
-with carve rays, integration with free-space carving.  Frame 0 initialises
-the map; the first W frames are warmup; K frames are timed.  All inputs are
-on the device before the timed region.
+with carve rays, integration with free-space carving.  The whole sequence is
+fused: frame 0 initialises the map, the frames up to the last K + W build it
+untimed, W warmup frames follow, and the last K frames are timed.  All
+inputs are on the device before the timed region (the host-to-device upload
+of a frame is measured apart, "h2d").
 
 Prints ONE JSON line.  Kernel durations are measured with HIP events on the
 stream the kernels run on.  "roofline" is the dominant kernel (the tracking
 sweep): its algorithmic bytes come from the host footprint of sampled frames
 (distinct voxel records and buckets a sweep reads, plus image bytes).
 "roofline_integrate" is the integration kernel, whose algorithmic bytes come
-from device counters of voxel updates.
+from device counters of voxel updates.  Extra measurements after the
+headline: the same sequence in FP16+u8 storage ("fp16", with its final pose
+against FP32's), with the clipping plane at 5 m ("depth_max_5m"), and the
+640x480 static room of 300 frames at 1 cm voxels ("static_room").  The CPU
+oracle is timed on a bounded sample of the headline sequence, single-thread
+and with all host cores ("cpu_baseline").
 """
 from __future__ import annotations
 
 import argparse
 import ctypes
 import json
+import math
 import os
 import sys
 import time
@@ -40,18 +50,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel, workload, storage):
+def profile_key(seq_name, n, storage, depth_max, K):
+    """The measurement a PMC summary applies to."""
+    return "%s:%d frames:%s:depth_max %.3g:last %d timed" % (seq_name, n, storage, depth_max, K)
+
+
+def traffic_from_profile(kernel, key):
     """(HBM bytes per launch, L2 hit rate) of `kernel` from the committed
-    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, calibrated; TCC_HIT /
-    (TCC_HIT + TCC_MISS)), if it was taken on the current kernel source
-    (else None, None)."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_%s_pmc.json" % (kernel.replace("_kernel", ""), workload, storage))
+    rocprofv3 PMC summary of the same measurement (FETCH_SIZE + WRITE_SIZE,
+    calibrated; TCC_HIT / (TCC_HIT + TCC_MISS)), if it was taken on the same
+    workload key (sequence, length, storage, depth_max, timed frames) and on
+    the current kernel source; else (None, None)."""
+    wl, _, st = key.split(":")[:3]
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_pmc.json" % (kernel.replace("_kernel", ""), wl, st))
     if not os.path.exists(path):
         return None, None
     with open(path) as fh:
         d = json.load(fh)
     from paper_1905_02082_amd.profiling import kernel_source_hash
-    if d.get("kernel_source_hash") != kernel_source_hash(kernel):
+    if d.get("kernel_source_hash") != kernel_source_hash(kernel) or d.get("workload") != key:
         return None, None
     return d.get("hbm_bytes_per_launch"), d.get("l2_hit_rate")
 
@@ -167,6 +184,10 @@ def virtual_depth_measurement(m, seq, frame, pose, reps=5):
     return res
 
 
+WORKLOAD_FRAMES = {"large_rooms": 1000, "static_room": 300, "dynamic_room": 400}
+WORKLOAD_BLOCKS = {"large_rooms": 3 << 20, "static_room": 1 << 18, "dynamic_room": 1 << 18}
+
+
 def make_sequence(workload, n):
     import synth
     if workload == "static_room":
@@ -178,13 +199,18 @@ def make_sequence(workload, n):
     raise SystemExit("unknown workload %s" % workload)
 
 
-def cpu_baseline(seq, budget_s=30.0):
-    """The oracle as it stands (single thread): frame 0 fusion, then full
-    frames until the time budget is spent; returns frames/s of the full
-    frames and the sample description."""
+def cpu_baseline(seq, budget_s=30.0, threads=1):
+    """The oracle as it stands: frame 0 fusion, then full frames until the
+    time budget is spent; returns frames/s of the full frames, the sample
+    description and the threads used.  threads > 1 runs the oracle's OpenMP
+    build (the same source, loops over pixels and blocks shared out) with
+    that many threads."""
     import oracle as O
-    a = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=64)
-    b = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=32)
+    lib = O.load_variant("omp" if threads > 1 else "serial")
+    if threads > 1:
+        lib.orc_set_threads(threads)
+    a = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=64, lib=lib)
+    b = O.OracleMap(seq.voxel_size, seq.truncation, seq.depth_max, 255, seq.carve_stride, real_bits=32, lib=lib)
     T = seq.poses[0]
     fr = O.Frame(seq.depth[0], seq.rgb[0], *seq.intrinsics, depth_scale=seq.depth_scale)
     T, _ = O.process_frame(a, fr, T, 0, seq.levels, seq.iters, mask_map=b)
@@ -197,9 +223,168 @@ def cpu_baseline(seq, budget_s=30.0):
         spent += time.perf_counter() - t0
         done += 1
         k += 1
-        log("cpu oracle frame %d: %.2f s" % (k - 1, spent / done))
-    return done / spent, "frames 1-%d of the same sequence (full method per frame after frame-0 fusion), " \
-                          "FP64 oracle + FP32 mask mirror, single thread" % done
+        log("cpu oracle (%d threads) frame %d: %.2f s" % (threads, k - 1, spent / done))
+    used = lib.orc_get_threads() if threads > 1 else 1
+    return done / spent, ("frames 1-%d of the headline sequence (full method per frame after frame-0 fusion), "
+                          "FP64 oracle + FP32 mask mirror, %s" % (done, "%d OpenMP threads" % used if threads > 1
+                                                                  else "single thread")), used
+
+
+def host_cpu():
+    """(logical CPUs usable by this process, CPU model name)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return n, model
+
+
+def upload_frames(seq, dev):
+    """Every frame of the sequence on the device (before any timed region)."""
+    import paper_1905_02082_amd as rf
+    return [rf.Frame.from_numpy(seq.depth[k], seq.rgb[k], *seq.intrinsics, depth_scale=seq.depth_scale,
+                                device=dev) for k in range(seq.n)]
+
+
+def h2d_measurement(seq, frames, ks, dev):
+    """Host-to-device upload of the frames ks from pinned host memory on the
+    stream the kernels use (HIP events): the PCIe share of a frame when the
+    frames start in host memory.  Never part of `value`."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    ms = []
+    for k in ks:
+        d = seq.depth[k]
+        dh = torch.from_numpy(np.ascontiguousarray(d).view(np.int16) if d.dtype == np.uint16
+                              else np.ascontiguousarray(d, np.float32)).pin_memory()
+        ch = torch.from_numpy(np.ascontiguousarray(seq.rgb[k])).pin_memory()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        frames[k].depth.copy_(dh, non_blocking=True)
+        frames[k].rgb.copy_(ch, non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms)), int(dh.numel() * dh.element_size() + ch.numel())
+
+
+def run_workload(seq, frames, storage, W, K, B, dev, name, depth_max=None):
+    """Fuses the sequence with the full method per frame; frames 0 .. n-K-W-1
+    build the map untimed, the next W are warmup, the last K are timed.
+    Returns the measurement dict (frames/s, latencies, stages, rooflines)."""
+    import numpy as np
+    import torch
+
+    import paper_1905_02082_amd as rf
+    n = seq.n
+    offset = 25  # batched sessions: session i starts i * offset frames later in the same sequence
+    n_run = n - offset * (B - 1)
+    if K + W > n_run - 1:
+        raise SystemExit("%s: --steps + --warmup must leave frame 0 before them (%d frames)" % (name, n_run))
+    dmax = seq.depth_max if depth_max is None else depth_max
+    mp = rf.MapParams(seq.voxel_size, seq.truncation, dmax, seq.num_buckets, WORKLOAD_BLOCKS[seq.name], 255,
+                      seq.carve_stride, storage, seq.width * seq.height)
+    tp = rf.TrackParams(seq.levels, seq.iters, 0.025, 64, 0.0)
+    mk = rf.MaskParams(0.5, 0.007)
+    sessions = [rf.Session(mp, seq.poses[offset * i], dev) for i in range(B)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    stage_names = ["track1", "mask", "track2", "allocate", "integrate"]
+
+    def step(k, ev=None):
+        rf.process_batch(sessions, [frames[offset * i + k] for i in range(B)], tp, mk, True, stream, ev)
+
+    first_timed = n_run - K
+    t0 = time.perf_counter()
+    for k in range(first_timed):
+        step(k)
+    torch.cuda.synchronize()
+    log("%s: fused %d frames untimed (%d map-building + %d warmup) in %.1f s" %
+        (name, first_timed, first_timed - W, W, time.perf_counter() - t0))
+    c0 = np.sum([s.map.cumulative_counts() for s in sessions], axis=0)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(K):
+        step(first_timed + i, events[i])
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    c1 = np.sum([s.map.cumulative_counts() for s in sessions], axis=0)
+    status = [s.map.status() for s in sessions]
+    flags = int(np.bitwise_or.reduce([f for f, _ in status]))
+    nblocks = int(status[0][1])
+    wall = t_end - t_start
+    per_stage = np.array([[events[i][j].elapsed_time(events[i][j + 1]) for j in range(5)] for i in range(K)])
+    frame_ms = np.array([events[i][0].elapsed_time(events[i][5]) for i in range(K)])
+    fps = B * K / wall
+    T_final = sessions[0].pose.cpu().numpy()
+
+    # tracking roofline: algorithmic bytes per sweep from the host footprint of
+    # sampled timed frames; duration = tracking stage time / launches (each
+    # pass is levels x iterations track_kernel launches plus one reset and one
+    # finalize launch of a few microseconds, counted in)
+    keys = sessions[0].map.export()[0].cpu().numpy()
+    sample = list(range(first_timed, n_run, max(1, K // 4)))[:4]
+    fp1, pix = track_footprint(seq, keys, sample, storage)
+    sweeps = seq.levels * seq.iters
+    track_alg = B * seq.iters * (2 * fp1.sum() + pix.sum()) / (2 * sweeps)
+    track_ms = float((per_stage[:, 0] + per_stage[:, 2]).mean()) / (2 * sweeps)
+    track_achieved = track_alg / (track_ms * 1e-3) / 1e9
+
+    # integration roofline: algorithmic bytes per launch from the voxel-update counters
+    band = c1[0] - c0[0]
+    free = c1[1] - c0[1]
+    blocks = c1[2] - c0[2]
+    map_frames = c1[3] - c0[3]                               # maps x frames integrated
+    rec = {"fp32": (8, 4), "fp16": (4, 4)}[storage]         # (sdf+weight, colour) bytes per voxel
+    img = seq.width * seq.height * (2 + 1 + 3)              # depth u16 + mask u8 + RGB8
+    alg_bytes = (band * 2 * (rec[0] + rec[1]) + free * 2 * rec[0] + blocks * (4 + 16) + map_frames * img)
+    alg_per_launch = alg_bytes / K                          # one integration launch per step
+    integ_ms = float(per_stage[:, 4].mean())
+    achieved = alg_per_launch / (integ_ms * 1e-3) / 1e9
+    key = profile_key(seq.name, n_run, storage, dmax, K) if B == 1 else None
+    traffic, l2_hit = traffic_from_profile("integrate_kernel", key) if key else (None, None)
+    track_traffic, track_l2_hit = traffic_from_profile("track_kernel", key) if key else (None, None)
+
+    E = np.linalg.inv(seq.poses[n_run - 1]) @ T_final       # session 0, against the generator's ground truth
+    out = {
+        "frames_per_s": round(fps, 3),
+        "ms_per_step": round(1000.0 * wall / K, 4),
+        "frames": n_run, "timed_frames": K, "warmup_frames": W, "map_building_frames": first_timed - W,
+        "storage": storage, "depth_max_m": dmax, "sessions": B,
+        "latency_ms": {"p50": round(float(np.percentile(frame_ms, 50)), 4),
+                       "p99": round(float(np.percentile(frame_ms, 99)), 4)},
+        "stages_ms": {nm: round(float(per_stage[:, j].mean()), 4) for j, nm in enumerate(stage_names)},
+        "roofline": {"kernel": "track_kernel", "bound": "hbm", "achieved": round(track_achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(track_achieved / HBM_PEAK_GBS, 4),
+                     "traffic": track_traffic, "l2_hit_rate": track_l2_hit,
+                     "alg_bytes_per_launch": int(track_alg), "avg_launch_ms": round(track_ms, 5),
+                     "launches_per_step": 2 * sweeps, "alg_bytes_per_level": [int(x) for x in fp1]},
+        "roofline_integrate": {"kernel": "integrate_kernel", "bound": "hbm", "achieved": round(achieved, 2),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                               "traffic": traffic, "l2_hit_rate": l2_hit,
+                               "alg_bytes_per_launch": int(alg_per_launch), "avg_launch_ms": round(integ_ms, 5),
+                               "band_updates_per_launch": int(band / K), "free_updates_per_launch": int(free / K),
+                               "blocks_per_launch": int(blocks / K)},
+        "map": {"blocks": nblocks, "flags": flags, "final_position_error_m": round(float(np.linalg.norm(E[:3, 3])), 5)},
+        "profile_key": key,
+    }
+    return out, sessions
+
+
+def workload_text(seq, r):
+    return ("%s %dx%d, %d frames (last %d timed), voxel %.3g m, truncation %.3g m, depth_max %.3g m, 8^3 blocks, "
+            "2^%d buckets, %d levels x %d GN iterations, %s storage, full dynamic pipeline per frame%s"
+            % (seq.name, seq.width, seq.height, r["frames"], r["timed_frames"], seq.voxel_size, seq.truncation,
+               r["depth_max_m"], int(round(math.log2(seq.num_buckets))), seq.levels, seq.iters, r["storage"],
+               "" if r["sessions"] == 1 else ", %d sessions per launch set" % r["sessions"]))
 
 
 def serving_bench(args):
@@ -259,12 +444,19 @@ def serving_bench(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=280, help="timed frames")
-    ap.add_argument("--warmup", type=int, default=20, help="untimed frames before the timed region")
-    ap.add_argument("--workload", default="static_room",
-                    choices=["static_room", "dynamic_room", "large_rooms", "serving"])
+    ap.add_argument("--steps", type=int, default=100, help="timed frames (the last frames of the sequence)")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed frames just before the timed ones")
+    ap.add_argument("--workload", default="large_rooms",
+                    choices=["large_rooms", "static_room", "dynamic_room", "serving"])
+    ap.add_argument("--frames", type=int, default=None,
+                    help="sequence length (default: 1000 large rooms, 300 static room, 400 dynamic room)")
     ap.add_argument("--storage", default=None, choices=["fp32", "fp16"],
                     help="voxel storage (default fp32; serving default fp16)")
+    ap.add_argument("--depth-max", type=float, default=None, help="clipping plane (default: the workload's)")
+    ap.add_argument("--extras", default="fp16,depth_max_5m,static_room",
+                    help="comma list of extra measurements after the headline: fp16 (same sequence, FP16+u8 "
+                         "storage), depth_max_5m (same sequence, clipping plane 5 m), static_room (300 frames), "
+                         "or none")
     ap.add_argument("--sessions", type=int, default=64, help="serving: concurrent sessions")
     ap.add_argument("--serve-scale", type=float, default=1.0, help="serving: scale of session lengths")
     ap.add_argument("--serve-src-frames", type=int, default=40, help="serving: rendered frames per source")
@@ -275,7 +467,7 @@ def main():
                     help="sessions processed together per step (1..8; the same scene at staggered frames)")
     ap.add_argument("--no-mesh", action="store_true", help="skip the mesh extraction measurement after the timed region")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time per cpu_baseline leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -294,142 +486,98 @@ def main():
     if args.workload == "serving":
         serving_bench(args)
         return
-    if args.storage is None:
-        args.storage = "fp32"
+    storage = args.storage or "fp32"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     W, K, B = args.warmup, args.steps, args.batch
-    n = W + K
-    if W < 1:
-        raise SystemExit("--warmup must be >= 1 (frame 0 initialises the map)")
+    if W < 0 or K < 1:
+        raise SystemExit("--steps must be >= 1 and --warmup >= 0")
     if not 1 <= B <= 8:
         raise SystemExit("--batch must be in [1, 8]")
-    offset = 25  # session i starts at frame i * offset of the same rendered sequence
+    extras = [] if args.extras in ("", "none") else args.extras.split(",")
+    order = ("fp16", "depth_max_5m", "static_room")  # static_room last: it replaces the uploaded frames
+    for e in extras:
+        if e not in order:
+            raise SystemExit("unknown extra %s" % e)
+    extras = [e for e in order if e in extras]
+    n = (args.frames or WORKLOAD_FRAMES[args.workload]) + 25 * (B - 1)
     t0 = time.perf_counter()
-    seq = make_sequence(args.workload, n + offset * (B - 1))
+    seq = make_sequence(args.workload, n)
     log("rendered %d frames %dx%d in %.1f s" % (seq.n, seq.width, seq.height, time.perf_counter() - t0))
-
-    max_blocks = {"static_room": 1 << 18, "dynamic_room": 1 << 18, "large_rooms": 3 << 20}[args.workload]
-    mp = rf.MapParams(seq.voxel_size, seq.truncation, seq.depth_max, seq.num_buckets, max_blocks, 255,
-                      seq.carve_stride, args.storage, seq.width * seq.height)
-    tp = rf.TrackParams(seq.levels, seq.iters, 0.025, 64, 0.0)
-    mk = rf.MaskParams(0.5, 0.007)
-    frames = [rf.Frame.from_numpy(seq.depth[k], seq.rgb[k], *seq.intrinsics, depth_scale=seq.depth_scale,
-                                  device=dev) for k in range(seq.n)]
-    sessions = [rf.Session(mp, seq.poses[offset * i], dev) for i in range(B)]
-    stream = torch.cuda.current_stream()
+    frames = upload_frames(seq, dev)
     torch.cuda.synchronize()
 
-    stage_names = ["track1", "mask", "track2", "allocate", "integrate"]
-
-    def step(k, ev=None):
-        rf.process_batch(sessions, [frames[offset * i + k] for i in range(B)], tp, mk, True, stream, ev)
-
-    # frame 0 initialises each map at its given pose; frames 1..W-1 warm up
-    for k in range(W):
-        step(k)
-    torch.cuda.synchronize()
-    c0 = np.sum([s.map.cumulative_counts() for s in sessions], axis=0)
-
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(K):
-        step(W + i, events[i])
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    c1 = np.sum([s.map.cumulative_counts() for s in sessions], axis=0)
-    status = [s.map.status() for s in sessions]
-    flags = int(np.bitwise_or.reduce([f for f, _ in status]))
-    nblocks = int(status[0][1])
-
-    wall = t_end - t_start
-    per_stage = np.array([[events[i][j].elapsed_time(events[i][j + 1]) for j in range(5)] for i in range(K)])
-    frame_ms = np.array([events[i][0].elapsed_time(events[i][5]) for i in range(K)])
-    fps = B * K / wall
-    T_final = sessions[0].pose.cpu().numpy()
-
-    # tracking roofline (the dominant kernel): algorithmic bytes per sweep from
-    # the host footprint of sampled frames; duration = tracking stage time /
-    # sweeps (each pass is levels x iterations track_kernel launches plus one
-    # reset and one finalize launch of a few microseconds, counted in)
-    keys = sessions[0].map.export()[0].cpu().numpy()
-    sample = list(range(W, n, max(1, K // 4)))[:4]
-    fp1, pix = track_footprint(seq, keys, sample, args.storage)
-    sweeps = seq.levels * seq.iters
-    track_alg = B * seq.iters * (2 * fp1.sum() + pix.sum()) / (2 * sweeps)
-    track_ms = float((per_stage[:, 0] + per_stage[:, 2]).mean()) / (2 * sweeps)
-    track_achieved = track_alg / (track_ms * 1e-3) / 1e9
-
-    # integration roofline: algorithmic bytes per launch from the voxel-update counters
-    band = c1[0] - c0[0]
-    free = c1[1] - c0[1]
-    blocks = c1[2] - c0[2]
-    map_frames = c1[3] - c0[3]                               # maps x frames integrated
-    rec = {"fp32": (8, 4), "fp16": (4, 4)}[args.storage]   # (sdf+weight, colour) bytes per voxel
-    img = seq.width * seq.height * (2 + 1 + 3)              # depth u16 + mask u8 + RGB8
-    alg_bytes = (band * 2 * (rec[0] + rec[1]) + free * 2 * rec[0] + blocks * (4 + 16) + map_frames * img)
-    launches = K                                            # one integration launch per step
-    alg_per_launch = alg_bytes / max(launches, 1)
-    integ_ms = float(per_stage[:, 4].mean())
-    achieved = alg_per_launch / (integ_ms * 1e-3) / 1e9
-    traffic, l2_hit = traffic_from_profile("integrate_kernel", args.workload, args.storage) if B == 1 else (None, None)
-    track_traffic, track_l2_hit = (traffic_from_profile("track_kernel", args.workload, args.storage) if B == 1
-                                   else (None, None))
-
-    # trajectory error against the generator's ground truth (context only)
-    E = np.linalg.inv(seq.poses[n - 1]) @ T_final       # session 0
-    ate_last = float(np.linalg.norm(E[:3, 3]))
-
+    head, sessions = run_workload(seq, frames, storage, W, K, B, dev, "headline", args.depth_max)
     out = {
         "metric": METRIC,
-        "value": round(fps, 3),
+        "value": head["frames_per_s"],
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(1000.0 * wall / K, 4),     # one step = one frame of every session
+        "ms_per_step": head["ms_per_step"],     # one step = one frame of every session
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "%s %dx%d, %d frames, voxel %.3g m, truncation %.3g m, 8^3 blocks, 2^%d buckets, "
-                               "%d levels x %d GN iterations, %s storage, full dynamic pipeline per frame%s"
-                               % (args.workload, seq.width, seq.height, n, seq.voxel_size, seq.truncation,
-                                  int(np.log2(seq.num_buckets)), seq.levels, seq.iters, args.storage,
-                                  "" if B == 1 else ", %d sessions per launch set" % B),
-                   "frames": n, "width": seq.width, "height": seq.height, "storage": args.storage,
-                   "sessions": B},
-        "latency_ms": {"p50": round(float(np.percentile(frame_ms, 50)), 4),
-                       "p99": round(float(np.percentile(frame_ms, 99)), 4)},
-        "stages_ms": {nm: round(float(per_stage[:, j].mean()), 4) for j, nm in enumerate(stage_names)},
-        "roofline": {"kernel": "track_kernel", "bound": "hbm", "achieved": round(track_achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(track_achieved / HBM_PEAK_GBS, 4),
-                     "traffic": track_traffic,
-                     "l2_hit_rate": track_l2_hit,
-                     "alg_bytes_per_launch": int(track_alg),
-                     "avg_launch_ms": round(track_ms, 5),
-                     "launches_per_step": 2 * sweeps,
-                     "alg_bytes_per_level": [int(x) for x in fp1]},
-        "roofline_integrate": {"kernel": "integrate_kernel", "bound": "hbm", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "l2_hit_rate": l2_hit,
-                     "alg_bytes_per_launch": int(alg_per_launch),
-                     "avg_launch_ms": round(integ_ms, 5),
-                     "band_updates_per_launch": int(band / max(launches, 1)),
-                     "free_updates_per_launch": int(free / max(launches, 1)),
-                     "blocks_per_launch": int(blocks / max(launches, 1))},
-        "map": {"blocks": nblocks, "flags": flags, "final_position_error_m": round(ate_last, 5)},
+        "config": {"workload": workload_text(seq, head), "frames": head["frames"],
+                   "map_building_frames": head["map_building_frames"], "width": seq.width,
+                   "height": seq.height, "storage": storage, "depth_max_m": head["depth_max_m"], "sessions": B},
     }
+    for k in ("latency_ms", "stages_ms", "roofline", "roofline_integrate", "map"):
+        out[k] = head[k]
+    out["profile_key"] = head["profile_key"]
+    h2d_ms, h2d_bytes = h2d_measurement(seq, frames, range(seq.n - min(K, 20), seq.n), dev)
+    out["h2d"] = {"ms_per_frame": round(h2d_ms, 4), "bytes_per_frame": h2d_bytes,
+                  "frames_per_s_incl_h2d": round(B * 1000.0 / (head["ms_per_step"] + B * h2d_ms), 3),
+                  "note": "pinned host -> device upload of a frame on the kernels' stream, timed apart and "
+                          "added serially (no copy/compute overlap); not part of value"}
     if not args.no_mesh and B == 1:
-        out["mesh"] = mesh_measurement(sessions[0].map, seq, args.storage)
-        out["virtual_depth"] = virtual_depth_measurement(sessions[0].map, seq, frames[n - 1], sessions[0].pose)
+        out["mesh"] = mesh_measurement(sessions[0].map, seq, storage)
+        out["virtual_depth"] = virtual_depth_measurement(sessions[0].map, seq, frames[seq.n - 1], sessions[0].pose)
+    pose_head = sessions[0].pose.cpu().numpy()
+    del sessions
+    torch.cuda.empty_cache()
+    if B == 1:
+        for e in extras:
+            if e == "fp16" and storage != "fp16":
+                r, ss = run_workload(seq, frames, "fp16", W, K, 1, dev, "fp16", args.depth_max)
+                Tf = ss[0].pose.cpu().numpy()
+                dT = np.linalg.inv(pose_head) @ Tf
+                r["final_pose_vs_fp32"] = {"dt_m": round(float(np.linalg.norm(dT[:3, 3])), 7),
+                                           "dr_rad": round(float(np.arccos(np.clip((np.trace(dT[:3, :3]) - 1) / 2,
+                                                                                   -1, 1))), 8)}
+                out["fp16"] = r
+            elif e == "depth_max_5m" and (args.depth_max or seq.depth_max) != 5.0:
+                r, ss = run_workload(seq, frames, storage, W, K, 1, dev, "depth_max_5m", 5.0)
+                out["depth_max_5m"] = r
+            elif e == "static_room" and args.workload != "static_room":
+                del frames
+                torch.cuda.empty_cache()
+                sq = make_sequence("static_room", WORKLOAD_FRAMES["static_room"])
+                fr2 = upload_frames(sq, dev)
+                r, ss = run_workload(sq, fr2, "fp32", W, K, 1, dev, "static_room")
+                r["workload"] = workload_text(sq, r)
+                out["static_room"] = r
+                del fr2
+                frames = None
+            else:
+                continue
+            del ss
+            torch.cuda.empty_cache()
+            if frames is None:
+                break
     if not args.no_cpu_baseline and B == 1:
-        v, sample = cpu_baseline(seq, args.cpu_budget)
-        out["cpu_baseline"] = {"value": round(v, 5), "unit": "frames/s", "cores": 1, "kind": "oracle",
-                               "sample": sample}
+        ncpu, model = host_cpu()
+        # all the host cores this process may use: the affinity set, capped by
+        # OMP_NUM_THREADS where the host assigns a share of its cores
+        share = int(os.environ.get("OMP_NUM_THREADS") or ncpu)
+        v1, sample1, _ = cpu_baseline(seq, args.cpu_budget, threads=1)
+        vn, samplen, used = cpu_baseline(seq, args.cpu_budget, threads=max(2, min(ncpu, share)))
+        out["cpu_baseline"] = {"value": round(vn, 5), "unit": "frames/s", "cores": used, "kind": "oracle",
+                               "sample": samplen, "cpu_model": model, "nproc": ncpu,
+                               "single_thread": {"value": round(v1, 5), "cores": 1, "sample": sample1}}
     print(json.dumps(out), flush=True)
 
 

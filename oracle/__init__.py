@@ -25,13 +25,22 @@ c_void_p, c_int, c_float, c_double, c_int64 = (ctypes.c_void_p, ctypes.c_int, ct
                                                ctypes.c_double, ctypes.c_int64)
 
 
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
+_variants = {}
+
+
 def build(force: bool = True) -> str:
+    """Compiles liboracle.so (single thread, what the tests use) and
+    liboracle_omp.so (the same source with OpenMP: loops over pixels and
+    blocks shared out over threads, sums and insertions kept in the serial
+    order, so its results are identical)."""
     src = os.path.join(_HERE, "refusion_oracle.cpp")
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
-                               "-shared", "-fPIC", src, "-o", tmp])
-        os.replace(tmp, _LIB_PATH)
+    for path, extra in ((_LIB_PATH, []), (_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", *extra,
+                                   "-shared", "-fPIC", src, "-o", tmp])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -42,12 +51,18 @@ class _Frame(ctypes.Structure):
 
 
 def _load():
+    return load_variant("serial")
+
+
+def load_variant(kind="serial"):
+    """The oracle library: "serial" (liboracle.so) or "omp" (liboracle_omp.so)."""
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
+    if kind in _variants:
+        return _variants[kind]
+    path = {"serial": _LIB_PATH, "omp": _OMP_PATH}[kind]
+    if not os.path.exists(path):
         build(force=False)
-    L = ctypes.CDLL(_LIB_PATH)
+    L = ctypes.CDLL(path)
     P = ctypes.POINTER
     sig = {
         "orc_map_new": (c_void_p, [c_int, c_int, c_float, c_float, c_float, c_int, c_int]),
@@ -76,12 +91,16 @@ def _load():
         "orc_dda": (c_int64, [c_void_p, c_void_p, c_void_p, c_int64]),
         "orc_floodfill": (None, [c_void_p, c_void_p, c_int, c_int, c_float, c_void_p]),
         "orc_morph3x3": (None, [c_void_p, c_int, c_int, c_int, c_void_p]),
+        "orc_set_threads": (None, [c_int]),
+        "orc_get_threads": (c_int, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = L
+    _variants[kind] = L
+    if kind == "serial":
+        _lib = L
     return L
 
 
@@ -118,8 +137,8 @@ def _mask_arg(mask, fr):
 
 class OracleMap:
     def __init__(self, voxel_size, truncation, depth_max=5.0, max_weight=255, carve_stride=4,
-                 real_bits=64, storage=0):
-        self.L = _load()
+                 real_bits=64, storage=0, lib=None):
+        self.L = _load() if lib is None else lib
         self.real_bits = real_bits
         self.h = self.L.orc_map_new(real_bits, storage, voxel_size, truncation, depth_max, max_weight,
                                     carve_stride)

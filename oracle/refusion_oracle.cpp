@@ -47,6 +47,10 @@
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include <vector>
 
 namespace {
 
@@ -371,7 +375,16 @@ void normal_equations(const Map<Real>& m, const Frame& f, const double* T, const
   for (int i = 0; i < 29; ++i) out[i] = 0;
   const int step = 1 << level;
   const double wc = (double)w_c;
-  for (int v = 0; v < f.H; v += step)
+  // The sums run over each row of the level (rows are independent), then
+  // over the rows in order, so the result does not depend on how rows are
+  // shared out over threads in the OpenMP build.
+  const int nv = (f.H + step - 1) / step;
+  std::vector<std::array<double, 29>> rows((size_t)nv);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int iv = 0; iv < nv; ++iv) {
+    const int v = iv*step;
+    std::array<double, 29>& acc = rows[iv];
+    acc.fill(0.0);
     for (int u = 0; u < f.W; u += step) {
       float D = depth_at(f, u, v);
       if (!depth_valid(D, m.P.depth_max)) continue;
@@ -384,13 +397,16 @@ void normal_equations(const Map<Real>& m, const Frame& f, const double* T, const
       int k = 0;
       for (int i = 0; i < 6; ++i)
         for (int j = i; j < 6; ++j) {
-          out[k++] += (double)pt.Jd[i]*(double)pt.Jd[j] + wc*((double)pt.Jc[i]*(double)pt.Jc[j]);
+          acc[k++] += (double)pt.Jd[i]*(double)pt.Jd[j] + wc*((double)pt.Jc[i]*(double)pt.Jc[j]);
         }
       for (int i = 0; i < 6; ++i)
-        out[21+i] += (double)pt.Jd[i]*(double)pt.rd + wc*((double)pt.Jc[i]*(double)pt.rc);
-      out[27] += (double)pt.rd*(double)pt.rd + wc*((double)pt.rc*(double)pt.rc);
-      out[28] += 1.0;
+        acc[21+i] += (double)pt.Jd[i]*(double)pt.rd + wc*((double)pt.Jc[i]*(double)pt.rc);
+      acc[27] += (double)pt.rd*(double)pt.rd + wc*((double)pt.rc*(double)pt.rc);
+      acc[28] += 1.0;
     }
+  }
+  for (const std::array<double, 29>& acc : rows)
+    for (int i = 0; i < 29; ++i) out[i] += acc[i];
 }
 
 // Solves (H + lambda diag H) delta = -g by Cholesky.  Returns false when a
@@ -481,6 +497,11 @@ void allocate(MapBase& m, const Frame& f, const double* T, const uint8_t* mask) 
   const float tau = P.truncation;
   m.last_F.clear();
   m.F_set.clear();
+  // The cells of every row's segments first (rows are independent), then
+  // their insertion in pixel order, so the map and F come out the same
+  // however the first loop is shared out over threads in the OpenMP build.
+  std::vector<std::vector<Key>> cells((size_t)f.H);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int v = 0; v < f.H; ++v)
     for (int u = 0; u < f.W; ++u) {
       float D = depth_at(f, u, v);
@@ -501,11 +522,12 @@ void allocate(MapBase& m, const Frame& f, const double* T, const uint8_t* mask) 
       transform(R, t, X1, P1);
       float q0[3], q1[3];
       for (int a = 0; a < 3; ++a) { q0[a] = P0[a]*iB; q1[a] = P1[a]*iB; }
-      dda_cells(q0, q1, [&](const int32_t* c) {
-        Key k{c[0], c[1], c[2]};
-        m.add_block(k);
-        if (m.F_set.insert(k).second) m.last_F.push_back(k);
-      });
+      dda_cells(q0, q1, [&](const int32_t* c) { cells[v].push_back(Key{c[0], c[1], c[2]}); });
+    }
+  for (const std::vector<Key>& row : cells)
+    for (const Key& k : row) {
+      m.add_block(k);
+      if (m.F_set.insert(k).second) m.last_F.push_back(k);
     }
 }
 
@@ -523,7 +545,12 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
   counts[0] = counts[1] = 0;
   std::vector<Key> F = m.last_F;
   std::sort(F.begin(), F.end());
-  for (const Key& b : F) {
+  // blocks are independent (each voxel is updated from its own value and the
+  // frame), so the OpenMP build shares them out over threads
+  int64_t n_band = 0, n_free = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_band, n_free)
+  for (size_t bi = 0; bi < F.size(); ++bi) {
+    const Key& b = F[bi];
     auto& blk = m.blocks.at(b);
     for (int l = 0; l < 512; ++l) {
       int32_t vi[3] = {8*b.x + (l & 7), 8*b.y + ((l >> 3) & 7), 8*b.z + (l >> 6)};
@@ -566,13 +593,15 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
           Real cn = std::nearbyint((W*(Real)vx.rgb[k] + (Real)c[k]) / (W + (Real)1));
           vx.rgb[k] = (uint8_t)std::min((Real)255, std::max((Real)0, cn));
         }
-        counts[0]++;
+        n_band++;
       } else {
-        counts[1]++;
+        n_free++;
       }
       vx.w = std::min(W + (Real)1, (Real)P.max_weight);
     }
   }
+  counts[0] = n_band;
+  counts[1] = n_free;
 }
 
 // Dynamics mask (Section III-C): r = S^2 at the registered pose (defined where
@@ -627,6 +656,7 @@ void dynamic_mask(const Map<float>& m, const Frame& f, const double* T, float ga
   const float tau = m.P.truncation;
   const float thr = gamma*(tau*tau);
   std::vector<float> Dff((size_t)W*H);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int v = 0; v < H; ++v)
     for (int u = 0; u < W; ++u) {
       size_t i = (size_t)v*W + u;
@@ -1142,6 +1172,24 @@ void orc_floodfill(const uint8_t* seeds, const float* D, int W, int H, float the
 
 void orc_morph3x3(const uint8_t* in, int W, int H, int erode, uint8_t* out) {
   morph3x3(in, W, H, erode != 0, out);
+}
+
+// Threads of the OpenMP build (the plain build runs one thread and ignores
+// the request).
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 }  // extern "C"
