@@ -44,18 +44,6 @@ struct Batch {
 static_assert(sizeof(Batch) <= 3072, "job batch must stay well inside the kernel-argument limit");
 
 // Job of workgroup g (uniform per workgroup).
-// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
-// b % 8), each XCD with its own L2.  xcd_contiguous renumbers them so that
-// each XCD takes one contiguous range of logical indices: tiles that are
-// neighbours in the image (and share voxels) then share one L2 instead of
-// being spread over all eight.  A bijection of [0, n).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_contiguous(int b, int n) {
-  const int per = n / kXcds, rem = n % kXcds;
-  const int x = b % kXcds, k = b / kXcds;
-  return x * per + min(x, rem) + k;
-}
-
 __device__ __forceinline__ int batch_job(const Batch& b, int g) {
   int j = 0;
   while (j + 1 < b.n && g >= b.base[j + 1]) ++j;

@@ -25,12 +25,11 @@ namespace rf {
 
 template <int DF, int STORAGE>
 __global__ __launch_bounds__(256) void residual_kernel(Batch b, float gamma) {
-  const int gb = xcd_contiguous(blockIdx.x, gridDim.x);  // neighbouring rows share an L2
-  const int jb = batch_job(b, gb);
+  const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const MapDev& m = J.m;
   const FrameDev& f = J.f;
-  const int idx = (gb - b.base[jb]) * blockDim.x + threadIdx.x;
+  const int idx = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
   if (idx >= f.W * f.H) return;
   const int u = idx % f.W, v = idx / f.W;
   const float D = load_depth<DF>(f, idx);

@@ -496,15 +496,14 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   __shared__ uint8_t s_gused[kWinCells];
   __shared__ int s_org[3];
   __shared__ uint32_t s_nref;
-  const int gb = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int jb = batch_job(b, gb);
+  const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const MapDev& m = J.m;
   const FrameDev& f = J.f;
   const uint8_t* mask = J.mask;
   double* user_pose = J.pose;
   rf_track_stats* stats = J.stats;
-  const int g0 = gb - b.base[jb];  // tile index within the job
+  const int g0 = blockIdx.x - b.base[jb];  // tile index within the job
   // Set only by earlier launches.  Read here but acted on after the pixel
   // loads and the solve are under way: only publishing waits for it.
   const uint32_t stopped = m.st->track_stop;
