@@ -190,6 +190,21 @@ rf_status track_normal_equations(rf_map* m, const rf_frame* f, const uint8_t* d_
 rf_status compute_dynamic_mask(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
                                uint8_t* d_mask_out, float* d_residual_out, void* stream);
 
+/* compute_dynamic_mask for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, but the flood fill's scratch (a
+ * per-pixel mask and two buffers of tile flags) lives in a static device
+ * array of the library, 4 MiB per GPU, held until the process ends, instead
+ * of the map arena.  The call allocates nothing.  Frames whose scratch
+ * (width*height bytes rounded up to 256, plus 8 bytes per 32x32 tile) exceeds
+ * 4 MiB -- about 4 million pixels -- are rejected with RF_ENOMEM before
+ * anything is enqueued; the map's max_pixels does not limit this variant.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams, or host threads) race and must be serialised by
+ * the caller.  Each call clears the tile flags it uses before the fill. */
+rf_status compute_dynamic_mask_static(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
+                                      uint8_t* d_mask_out, float* d_residual_out, void* stream);
+
 /* compute_dynamic_mask that also writes its intermediate masks (each nullable,
  * device uint8 width*height): raw threshold, eroded seeds M_R, flood fill M_D. */
 rf_status compute_dynamic_mask_stages(rf_map* m, const rf_frame* f, const double* d_pose,

@@ -70,6 +70,8 @@ EXPORTS = {
                                          c_float, c_void_p, c_void_p]),
     "compute_dynamic_mask": (c_int32, [c_void_p, ctypes.POINTER(RfFrame), c_void_p,
                                        ctypes.POINTER(RfMaskParams), c_void_p, c_void_p, c_void_p]),
+    "compute_dynamic_mask_static": (c_int32, [c_void_p, ctypes.POINTER(RfFrame), c_void_p,
+                                              ctypes.POINTER(RfMaskParams), c_void_p, c_void_p, c_void_p]),
     "compute_dynamic_mask_stages": (c_int32, [c_void_p, ctypes.POINTER(RfFrame), c_void_p,
                                               ctypes.POINTER(RfMaskParams), c_void_p, c_void_p, c_void_p,
                                               c_void_p, c_void_p, c_void_p]),

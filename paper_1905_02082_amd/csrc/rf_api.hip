@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -166,6 +167,40 @@ rf_status mask_checks(const rf_job& j, rf::Job& J) {
   return RF_OK;
 }
 
+// ------------------------------------------- allocation-free mask variant
+// compute_dynamic_mask_static keeps the flood fill's per-pixel mask and its
+// two buffers of tile flags in this file-scope device array instead of the
+// map arena.  Each GPU holds its own copy at its own address until the
+// process ends; host code uses only the address hipGetSymbolAddress returns
+// for the current device, never the array's name.
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+rf_status static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(RF_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RF_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(RF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RF_OK;
+}
+
+__global__ void clear_words_kernel(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
 }  // namespace
 
 extern "C" {
@@ -323,6 +358,49 @@ rf_status compute_dynamic_mask_stages(rf_map* m, const rf_frame* f, const double
 rf_status compute_dynamic_mask(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
                                uint8_t* d_mask_out, float* d_residual_out, void* stream) {
   return compute_dynamic_mask_stages(m, f, d_pose, mp, nullptr, nullptr, nullptr, d_mask_out, d_residual_out, stream);
+}
+
+rf_status compute_dynamic_mask_static(rf_map* m, const rf_frame* f, const double* d_pose, const rf_mask_params* mp,
+                                      uint8_t* d_mask_out, float* d_residual_out, void* stream) {
+  if (!m || !d_pose || !mp || !d_mask_out || !f) return fail(RF_EINVAL, "map/pose/params/out/frame is NULL");
+  if (!(mp->gamma >= 0.0f) || !(mp->theta >= 0.0f)) return fail(RF_EINVAL, "gamma and theta must be >= 0");
+  rf::FrameDev fd;
+  rf_status st = make_frame(f, fd);
+  if (st) return st;
+  // the flood fill's scratch: the per-pixel mask, then two buffers of tile flags
+  const size_t npx = (size_t)fd.W * (size_t)fd.H;
+  const uint32_t tiles = (uint32_t)((fd.W + rf::kTile - 1) / rf::kTile) * (uint32_t)((fd.H + rf::kTile - 1) / rf::kTile);
+  const size_t flags_at = align256(npx);
+  const size_t need = flags_at + (size_t)2 * tiles * 4;
+  if (need > kStaticScratchBytes)
+    return fail(RF_ENOMEM, "compute_dynamic_mask_static: a %dx%d frame needs %zu bytes of scratch, the static "
+                "array holds %zu", fd.W, fd.H, need, kStaticScratchBytes);
+  void* base = nullptr;
+  st = static_scratch(&base);
+  if (st) return st;
+  uint8_t* sp = static_cast<uint8_t*>(base);
+  rf_job j{};
+  j.map = m;
+  j.frame = *f;
+  j.d_pose = const_cast<double*>(d_pose);
+  j.d_mask_out = d_mask_out;
+  auto fill = [&](const rf_job& jj, rf::Job& J) -> rf_status {
+    if (!jj.d_mask_out) return fail(RF_EINVAL, "compute_dynamic_mask_static: mask output is NULL");
+    J.pose = jj.d_pose;
+    J.mask_out = jj.d_mask_out;
+    J.residual = d_residual_out;
+    J.m.md = sp;
+    J.m.dirty = reinterpret_cast<uint32_t*>(sp + flags_at);
+    J.m.dirty_cap = tiles;
+    return RF_OK;
+  };
+  auto launch = [&](rf::Batch& b, int df, int sto) {
+    // the tile flags must start empty; the last call on this device may
+    // have used other sizes (a fill kernel, no memset node in a captured graph)
+    clear_words_kernel<<<(2 * tiles + 255) / 256, 256, 0, S(stream)>>>(b.job[0].m.dirty, 2 * tiles);
+    rf::launch_mask(b, df, sto, *mp, S(stream));
+  };
+  return run_batches(&j, 1, "compute_dynamic_mask_static", fill, launch);
 }
 
 // ---------------------------------------------------------------- batched entry points
