@@ -65,7 +65,9 @@ def load_variant(kind="serial"):
     L = ctypes.CDLL(path)
     P = ctypes.POINTER
     sig = {
-        "orc_map_new": (c_void_p, [c_int, c_int, c_float, c_float, c_float, c_int, c_int]),
+        "orc_map_new": (c_void_p, [c_int, c_int, c_float, c_float, c_float, c_int, c_int, c_int]),
+        "orc_map_num_voxel_blocks": (c_int64, [c_void_p]),
+        "orc_export_free": (c_int64, [c_void_p, c_void_p, c_void_p, c_int64]),
         "orc_map_free": (None, [c_void_p]),
         "orc_map_num_blocks": (c_int64, [c_void_p]),
         "orc_allocate": (c_int64, [c_void_p, P(_Frame), c_void_p, c_void_p, c_void_p, c_int64]),
@@ -137,11 +139,11 @@ def _mask_arg(mask, fr):
 
 class OracleMap:
     def __init__(self, voxel_size, truncation, depth_max=5.0, max_weight=255, carve_stride=4,
-                 real_bits=64, storage=0, lib=None):
+                 real_bits=64, storage=0, lib=None, free_blocks=0):
         self.L = _load() if lib is None else lib
         self.real_bits = real_bits
         self.h = self.L.orc_map_new(real_bits, storage, voxel_size, truncation, depth_max, max_weight,
-                                    carve_stride)
+                                    carve_stride, free_blocks)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -151,6 +153,19 @@ class OracleMap:
     @property
     def num_blocks(self):
         return self.L.orc_map_num_blocks(self.h)
+
+    @property
+    def num_voxel_blocks(self):
+        """Blocks holding voxels (with compact free space: not the free blocks)."""
+        return self.L.orc_map_num_voxel_blocks(self.h)
+
+    def export_free(self):
+        """Compact free space: (sorted (n,3) int32 keys, (n,) weights) of the free blocks."""
+        n = self.L.orc_export_free(self.h, None, None, 0)
+        keys = np.zeros((n, 3), np.int32)
+        w = np.zeros(n, np.float64)
+        self.L.orc_export_free(self.h, keys.ctypes.data, w.ctypes.data, n)
+        return keys, w
 
     def allocate(self, fr: Frame, pose, mask=None):
         """Returns the sorted (n,3) int32 keys of the blocks visited this frame."""
@@ -164,9 +179,9 @@ class OracleMap:
     def integrate(self, fr: Frame, pose, mask=None):
         T = np.ascontiguousarray(pose, np.float64)
         m = _mask_arg(mask, fr)
-        counts = np.zeros(2, np.int64)
+        counts = np.zeros(3, np.int64)
         self.L.orc_integrate(self.h, ctypes.byref(fr.s), T.ctypes.data, _ptr(m), counts.ctypes.data)
-        return counts
+        return counts  # band updates, free-space updates, blocks carved whole (compact free space)
 
     def normal_equations(self, fr: Frame, pose, level=0, w_c=0.025, mask=None):
         T = np.ascontiguousarray(pose, np.float64)

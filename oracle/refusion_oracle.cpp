@@ -192,7 +192,8 @@ inline Real luminance(const uint8_t* c) {
 struct Params {
   float voxel_size, truncation, depth_max;
   int max_weight, carve_stride;
-  int storage;  // 0: Real; 1: mirror of FP16 sdf/tau + u8 weight storage
+  int storage;      // 0: Real; 1: mirror of FP16 sdf/tau + u8 weight storage
+  int free_blocks;  // 1: compact free space (blocks carved whole, free blocks without voxels)
 };
 
 struct MapBase {
@@ -201,6 +202,7 @@ struct MapBase {
   std::vector<Key> last_F;  // blocks visited by the last allocation
   std::unordered_set<Key, KeyHash> F_set;
   virtual int64_t num_blocks() const = 0;
+  virtual int64_t num_voxel_blocks() const = 0;
   virtual bool has_block(const Key& k) const = 0;
   virtual void add_block(const Key& k) = 0;
 };
@@ -212,18 +214,32 @@ struct Voxel {
   uint8_t rgb[3] = {0, 0, 0};
 };
 
+// Compact free space (P.free_blocks = 1; the octree or free-space
+// representation that Sec. III-D leaves to future work, read here as coarse
+// free-block flags): a block that has only ever been carved whole is a free
+// block, kept as one voxel value (sdf tau, weight = the number of frames that
+// carved it, capped; unobserved while that is 0) that every one of its 512
+// voxels reads as.  It becomes an ordinary block of voxels, all starting from
+// that value, the first time a frame does not carve it whole.
 template <class Real>
 struct Map : MapBase {
   std::unordered_map<Key, std::vector<Voxel<Real>>, KeyHash> blocks;
-  int64_t num_blocks() const override { return (int64_t)blocks.size(); }
-  bool has_block(const Key& k) const override { return blocks.count(k) != 0; }
+  std::unordered_map<Key, Voxel<Real>, KeyHash> free_blk;  // free blocks (P.free_blocks)
+  int64_t num_blocks() const override { return (int64_t)(blocks.size() + free_blk.size()); }
+  int64_t num_voxel_blocks() const override { return (int64_t)blocks.size(); }
+  bool has_block(const Key& k) const override { return blocks.count(k) != 0 || free_blk.count(k) != 0; }
   void add_block(const Key& k) override {
-    if (!blocks.count(k)) blocks.emplace(k, std::vector<Voxel<Real>>(512));
+    if (has_block(k)) return;
+    if (P.free_blocks) free_blk.emplace(k, Voxel<Real>());
+    else blocks.emplace(k, std::vector<Voxel<Real>>(512));
   }
   const Voxel<Real>* voxel(int32_t vx, int32_t vy, int32_t vz) const {
     Key k{floor_div8(vx), floor_div8(vy), floor_div8(vz)};
     auto it = blocks.find(k);
-    if (it == blocks.end()) return nullptr;
+    if (it == blocks.end()) {
+      auto jt = free_blk.find(k);
+      return jt == free_blk.end() ? nullptr : &jt->second;
+    }
     int lx = vx - 8*k.x, ly = vy - 8*k.y, lz = vz - 8*k.z;
     return &it->second[lx + 8*ly + 64*lz];
   }
@@ -534,24 +550,128 @@ void allocate(MapBase& m, const Frame& f, const double* T, const uint8_t* mask) 
 // Integration (Sections III-A, III-C, III-D): running weighted average of the
 // truncated projective distance, free space carved to tau, masked pixels
 // ignored.  Decisions in FP32; values in Real.
+// Whole-block carving test of the compact free-space reading (FP32, in
+// this order in the kernels too).  Depth cells: per 8x8 pixels, the
+// smallest depth of the cell's measured pixels (D > 0, also beyond the
+// clipping plane), or 0 when a pixel of the cell is masked or none is
+// measured.  A block is carved whole when its 8 corner voxels, transformed
+// as the integration transforms voxels, lie more than 1 mm in front of the
+// camera and at least 1 mm before the clipping plane, the nearest pixels of
+// their projections, widened by one pixel, span a rectangle inside the
+// image covering at most 64 cells, and every one of those cells holds a
+// depth more than tau + 1 mm beyond the block's farthest corner.  With every
+// pixel measured and unmasked, the per-voxel rule would then carve every
+// voxel of the block (the voxels' depths and pixels lie within the corners'
+// range, far inside the margins); unmeasured pixels inside the rectangle
+// are carved over.
+constexpr int kCell = 8;
+
+std::vector<float> depth_cells(const Frame& f, const uint8_t* mask, int& cw) {
+  cw = (f.W + kCell - 1) / kCell;
+  const int ch = (f.H + kCell - 1) / kCell;
+  std::vector<float> cells((size_t)cw*ch);
+  for (int cv = 0; cv < ch; ++cv)
+    for (int cu = 0; cu < cw; ++cu) {
+      float e = INFINITY;
+      bool masked = false;
+      for (int v = cv*kCell; v < std::min(cv*kCell + kCell, f.H); ++v)
+        for (int u = cu*kCell; u < std::min(cu*kCell + kCell, f.W); ++u) {
+          if (mask && mask[(size_t)v*f.W + u]) masked = true;
+          float D = depth_at(f, u, v);
+          if (D > 0.0f) e = std::min(e, D);
+        }
+      cells[(size_t)cv*cw + cu] = (masked || e == INFINITY) ? 0.0f : e;
+    }
+  return cells;
+}
+
+bool carve_whole(const Params& P, const Frame& f, const std::vector<float>& cells, int cw, const float R[9],
+                 const float t[3], const Key& b) {
+  const float s = P.voxel_size, margin = 1.0e-3f;
+  float zmin = INFINITY, zmax = -INFINITY, umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+  for (int k = 0; k < 8; ++k) {
+    int32_t vi[3] = {8*b.x + ((k & 1) ? 7 : 0), 8*b.y + ((k & 2) ? 7 : 0), 8*b.z + ((k & 4) ? 7 : 0)};
+    float d[3], X[3];
+    for (int a = 0; a < 3; ++a) d[a] = (float)vi[a]*s - t[a];
+    for (int j = 0; j < 3; ++j) X[j] = (R[j]*d[0] + R[3+j]*d[1]) + R[6+j]*d[2];
+    zmin = std::min(zmin, X[2]);
+    zmax = std::max(zmax, X[2]);
+    const float zz = std::max(X[2], margin);
+    const float uf = f.fx*(X[0]/zz) + f.cx, vf = f.fy*(X[1]/zz) + f.cy;
+    umin = std::min(umin, uf); umax = std::max(umax, uf);
+    vmin = std::min(vmin, vf); vmax = std::max(vmax, vf);
+  }
+  if (!(zmin > margin && zmax + margin <= P.depth_max)) return false;
+  const float u0 = std::floor(umin + 0.5f) - 1.0f, u1 = std::floor(umax + 0.5f) + 1.0f;
+  const float v0 = std::floor(vmin + 0.5f) - 1.0f, v1 = std::floor(vmax + 0.5f) + 1.0f;
+  if (!(u0 >= 0.0f && v0 >= 0.0f && u1 <= (float)(f.W - 1) && v1 <= (float)(f.H - 1))) return false;
+  const int c0 = (int)u0 / kCell, c1 = (int)u1 / kCell, r0 = (int)v0 / kCell, r1 = (int)v1 / kCell;
+  if ((c1 - c0 + 1)*(r1 - r0 + 1) > 64) return false;
+  float dmin = INFINITY;
+  for (int r = r0; r <= r1; ++r)
+    for (int c = c0; c <= c1; ++c) dmin = std::min(dmin, cells[(size_t)r*cw + c]);
+  return dmin > zmax + P.truncation + margin;
+}
+
+// Integration (Sections III-A, III-C, III-D): running weighted average of the
+// truncated projective distance, free space carved to tau, masked pixels
+// ignored.  Decisions in FP32; values in Real.  counts: band updates, free
+// updates, blocks carved whole (compact free space: free blocks counted
+// once, their voxels not counted as updates).
 template <class Real>
-void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mask, int64_t counts[2]) {
+void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mask, int64_t counts[3]) {
   const Params& P = m.P;
   float Rf[9], tf[3];
   pose_split<float>(T, Rf, tf);
   Real Rr[9], tr[3];
   pose_split<Real>(T, Rr, tr);
   const float s = P.voxel_size, tau = P.truncation, zclip = P.depth_max;
-  counts[0] = counts[1] = 0;
+  counts[0] = counts[1] = counts[2] = 0;
   std::vector<Key> F = m.last_F;
   std::sort(F.begin(), F.end());
+  // compact free space: the whole-block test of every listed block; a free
+  // block carved whole only counts the frame, any other free block becomes
+  // a block of voxels before the voxel updates
+  std::vector<char> whole(F.size(), 0);
+  int64_t n_whole = 0;
+  if (P.free_blocks) {
+    int cw = 0;
+    const std::vector<float> cells = depth_cells(f, mask, cw);
+    for (size_t bi = 0; bi < F.size(); ++bi) {
+      whole[bi] = carve_whole(P, f, cells, cw, Rf, tf, F[bi]) ? 1 : 0;
+      n_whole += whole[bi];
+      auto it = m.free_blk.find(F[bi]);
+      if (it == m.free_blk.end()) continue;
+      if (whole[bi]) {
+        Voxel<Real>& fv = it->second;
+        fv.sdf = (Real)tau;
+        fv.w = std::min(fv.w + (Real)1, (Real)P.max_weight);
+        whole[bi] = 2;  // done
+      } else {
+        m.blocks.emplace(F[bi], std::vector<Voxel<Real>>(512, it->second));
+        m.free_blk.erase(it);
+      }
+    }
+  }
   // blocks are independent (each voxel is updated from its own value and the
   // frame), so the OpenMP build shares them out over threads
   int64_t n_band = 0, n_free = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_band, n_free)
   for (size_t bi = 0; bi < F.size(); ++bi) {
     const Key& b = F[bi];
+    if (whole[bi] == 2) continue;  // free block carved whole
     auto& blk = m.blocks.at(b);
+    if (whole[bi]) {
+      // carved whole: every voxel takes the free-space update
+      for (int l = 0; l < 512; ++l) {
+        Voxel<Real>& vx = blk[l];
+        Real W = vx.w;
+        vx.sdf = m.store_sdf((W*vx.sdf + (Real)tau) / (W + (Real)1));
+        vx.w = std::min(W + (Real)1, (Real)P.max_weight);
+      }
+      n_free += 512;
+      continue;
+    }
     for (int l = 0; l < 512; ++l) {
       int32_t vi[3] = {8*b.x + (l & 7), 8*b.y + ((l >> 3) & 7), 8*b.z + (l >> 6)};
       // --- FP32 decision path: X = R^T (v s - t)
@@ -602,6 +722,7 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
   }
   counts[0] = n_band;
   counts[1] = n_free;
+  counts[2] = n_whole;
 }
 
 // Dynamics mask (Section III-C): r = S^2 at the registered pose (defined where
@@ -899,12 +1020,12 @@ static Frame to_frame(const orc_frame* f) {
 }
 
 void* orc_map_new(int real_bits, int storage, float voxel_size, float truncation, float depth_max,
-                  int max_weight, int carve_stride) {
+                  int max_weight, int carve_stride, int free_blocks) {
   OrcMap* h = new OrcMap;
   h->real_bits = real_bits;
   if (real_bits == 32) h->m = new Map<float>();
   else h->m = new Map<double>();
-  h->m->P = Params{voxel_size, truncation, depth_max, max_weight, carve_stride, storage};
+  h->m->P = Params{voxel_size, truncation, depth_max, max_weight, carve_stride, storage, free_blocks};
   return h;
 }
 
@@ -915,6 +1036,9 @@ void orc_map_free(void* p) {
 }
 
 int64_t orc_map_num_blocks(void* p) { return ((OrcMap*)p)->m->num_blocks(); }
+
+// Blocks that hold voxels (all blocks unless the map keeps free space compact).
+int64_t orc_map_num_voxel_blocks(void* p) { return ((OrcMap*)p)->m->num_voxel_blocks(); }
 
 // Allocation; returns |F| and writes F's keys (sorted) if out_keys != NULL.
 int64_t orc_allocate(void* p, const orc_frame* fr, const double* T, const uint8_t* mask,
@@ -932,10 +1056,10 @@ int64_t orc_allocate(void* p, const orc_frame* fr, const double* T, const uint8_
 
 int orc_integrate(void* p, const orc_frame* fr, const double* T, const uint8_t* mask, int64_t* counts) {
   OrcMap* h = (OrcMap*)p;
-  int64_t c[2];
+  int64_t c[3];
   if (h->real_bits == 32) integrate(*as<float>(h->m), to_frame(fr), T, mask, c);
   else integrate(*as<double>(h->m), to_frame(fr), T, mask, c);
-  if (counts) { counts[0] = c[0]; counts[1] = c[1]; }
+  if (counts) { counts[0] = c[0]; counts[1] = c[1]; counts[2] = c[2]; }
   return 0;
 }
 
@@ -1063,6 +1187,24 @@ int64_t orc_export(void* p, int32_t* keys, double* sdf, double* w, uint8_t* rgb,
         if (w) w[512*i + l] = (double)blk[l].w;
         if (rgb) for (int k = 0; k < 3; ++k) rgb[3*(512*i + l) + k] = blk[l].rgb[k];
       }
+    }
+    return (int64_t)ks.size();
+  };
+  if (h->real_bits == 32) return dump(as<float>(h->m));
+  return dump(as<double>(h->m));
+}
+
+// Free blocks (compact free space): keys (sorted) and the weight their voxels
+// read as.  Returns the count.
+int64_t orc_export_free(void* p, int32_t* keys, double* w, int64_t cap) {
+  OrcMap* h = (OrcMap*)p;
+  auto dump = [&](auto* m) -> int64_t {
+    std::vector<Key> ks;
+    for (auto& kv : m->free_blk) ks.push_back(kv.first);
+    std::sort(ks.begin(), ks.end());
+    for (int64_t i = 0; i < (int64_t)ks.size() && i < cap; ++i) {
+      if (keys) { keys[3*i] = ks[i].x; keys[3*i+1] = ks[i].y; keys[3*i+2] = ks[i].z; }
+      if (w) w[i] = (double)m->free_blk.at(ks[i]).w;
     }
     return (int64_t)ks.size();
   };

@@ -1,0 +1,210 @@
+"""Pins of the oracle's compact free space (the free-space representation
+that Sec. III-D leaves to future work, read as coarse free-block flags; map
+option free_blocks=1), against closed forms and against the per-voxel
+carving of Sec. III-D (no GPU).
+
+Reading: a block whose 8 corner voxels lie in front of the clipping plane
+and project, with a one-pixel border, into a part of the image where every
+8x8 cell has a measured, unmasked depth more than tau (+1 mm) beyond the
+block's farthest corner is carved whole (every voxel takes the free-space
+update).  A block that has only ever been carved whole is a free block: no
+voxels, one value (sdf tau, weight = frames that carved it) that all its
+voxels read as; it becomes a block of voxels starting from that value the
+first time a frame does not carve it whole."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from synth import analytic as A
+
+
+def plane_frame(d, W=40, H=30, f=30.0, holes=None, color=(200, 100, 50)):
+    depth = np.full((H, W), d, np.float32)
+    if holes is not None:
+        depth[holes] = 0.0
+    rgb = np.zeros((H, W, 3), np.uint8)
+    rgb[:] = color
+    return O.Frame(depth, rgb, f, f, (W - 1) / 2, (H - 1) / 2)
+
+
+def maps(s, tau, bits=64, dmax=5.0, stride=2, storage=0):
+    return (O.OracleMap(s, tau, dmax, 255, stride, real_bits=bits, storage=storage),
+            O.OracleMap(s, tau, dmax, 255, stride, real_bits=bits, storage=storage, free_blocks=1))
+
+
+def voxels_by_key(m):
+    keys, sdf, w, rgb = m.export()
+    return {tuple(k): (sdf[i], w[i], rgb[i]) for i, k in enumerate(keys)}
+
+
+def fuse(m, frames, poses, masks=None):
+    out = []
+    for i, (fr, T) in enumerate(zip(frames, poses)):
+        mk = None if masks is None else masks[i]
+        m.allocate(fr, T, mk)
+        out.append(m.integrate(fr, T, mk))
+    return out
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_first_frame_equals_per_voxel_carving(bits):
+    """With every pixel measured, the first frame of the compact map reads
+    exactly like the per-voxel map: voxel blocks hold identical voxels, and
+    every voxel of a free block was carved once by the per-voxel rule (sdf
+    tau, weight 1) -- the block test is sound."""
+    room = synth.parity_room(n_frames=3)
+    fr = O.Frame(room.depth[0], room.rgb[0], *room.intrinsics)
+    assert (room.depth[0] > 0).all()
+    a, b = maps(room.voxel_size, room.truncation, bits, room.depth_max, room.carve_stride)
+    fuse(a, [fr], [room.poses[0]])
+    cnt = fuse(b, [fr], [room.poses[0]])[0]
+    full = voxels_by_key(a)
+    comp = voxels_by_key(b)
+    fk, fw = b.export_free()
+    assert len(fk) > 20 and cnt[2] >= len(fk)
+    assert b.num_blocks == a.num_blocks == len(comp) + len(fk)
+    for k, (sdf, w, rgb) in comp.items():
+        s2, w2, c2 = full[k]
+        assert np.array_equal(sdf, s2) and np.array_equal(w, w2) and np.array_equal(rgb, c2)
+    tau = float(np.float32(room.truncation))
+    for k, wk in zip(map(tuple, fk), fw):
+        sdf, w, rgb = full[k]
+        assert wk == 1 and np.all(w == 1) and np.all(rgb == 0)
+        assert np.all(np.abs(sdf - tau) <= (2e-16 if bits == 64 else 1e-8))
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_free_block_reads_tau_and_counts_frames(bits):
+    """A wall 1.4 m away seen n times: blocks wholly in front of it are free
+    blocks of weight n whose voxels read (tau, n); the voxel blocks at the
+    wall hold d - z in the band, as the per-voxel rule gives; free space
+    costs no voxel storage."""
+    s, tau, d, n = 0.02, 0.06, 1.4, 5
+    a, b = maps(s, tau, bits)
+    fr = plane_frame(d)
+    fuse(a, [fr] * n, [np.eye(4)] * n)
+    fuse(b, [fr] * n, [np.eye(4)] * n)
+    fk, fw = b.export_free()
+    assert len(fk) > 50 and np.all(fw == n)
+    assert b.num_voxel_blocks + len(fk) == a.num_voxel_blocks  # free space costs no voxels
+    # free blocks read tau with weight n at every voxel (through the sampler)
+    for k in fk:
+        y = (8 * k.astype(np.float64) + 3.25) * float(np.float32(s))  # a cell inside the block
+        ok, out = b.sample(y)
+        assert ok and out[0] == float(np.float32(tau)) and np.all(out[1:4] == 0)
+    # voxel blocks equal the per-voxel map (every voxel there was updated
+    # identically: the same frame each time, blocks never switch)
+    full = voxels_by_key(a)
+    for k, (sdf, w, rgb) in voxels_by_key(b).items():
+        assert np.array_equal(sdf, full[k][0]) and np.array_equal(w, full[k][1])
+    D = float(np.float32(d))
+    keys, sdf, w, _ = b.export()
+    cen = A.block_voxel_centres(keys, s).reshape(-1, 3)
+    band = (w.reshape(-1) == n) & (np.abs(D - cen[:, 2]) < tau - 1e-6)
+    assert band.sum() > 100
+    np.testing.assert_allclose(sdf.reshape(-1)[band], D - cen[band, 2], atol=1e-12 if bits == 64 else 2e-7)
+
+
+def test_moved_object_still_fades():
+    """A wall at 0.9 m for 4 frames, then at 1.6 m: the voxels of the old
+    wall decay toward tau by the running-average recurrence, whether their
+    blocks are carved whole or voxel by voxel; free blocks in front of both
+    walls count all 7 frames."""
+    s, tau = 0.02, 0.06
+    _, b = maps(s, tau)
+    near, far = plane_frame(0.9), plane_frame(1.6)
+    fuse(b, [near] * 4, [np.eye(4)] * 4)
+    k0, sdf0, w0, _ = b.export()
+    fuse(b, [far] * 3, [np.eye(4)] * 3)
+    k1, sdf1, w1, _ = b.export()
+    old = {tuple(k): i for i, k in enumerate(k0)}
+    cen = A.block_voxel_centres(k1, s)
+    checked = 0
+    for i, k in enumerate(map(tuple, k1)):
+        if k not in old:
+            continue
+        j = old[k]
+        c = cen[i]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            inside = (c[:, 2] > 0) & (np.abs(30 * c[:, 0] / c[:, 2]) < 18) & (np.abs(30 * c[:, 1] / c[:, 2]) < 13)
+        was_band = (w0[j] == 4) & (np.abs(0.9 - c[:, 2]) < tau - 1e-3) & inside & (c[:, 2] < 1.6 - tau - 1e-3)
+        ref = sdf0[j].copy()
+        W = w0[j].copy()
+        for _ in range(3):
+            ref = (W * ref + float(np.float32(tau))) / (W + 1)
+            W = W + 1
+        np.testing.assert_allclose(sdf1[i][was_band], ref[was_band], rtol=0, atol=1e-15)
+        assert np.all(w1[i][was_band] == 7)
+        checked += was_band.sum()
+    assert checked > 100
+    fk, fw = b.export_free()
+    front = A.block_voxel_centres(fk, s)[:, :, 2].max(1) < 0.9 - tau - 0.02
+    assert front.sum() > 10 and np.all(fw[front] == 7)
+
+
+def test_unmeasured_pixels_are_carved_over_masked_are_not():
+    """Pixels without a measurement inside a block's image rectangle do not
+    stop it being carved whole (the per-voxel rule leaves the voxels that
+    project onto them untouched); a masked pixel does."""
+    s, tau, d = 0.02, 0.06, 1.4
+    holes = np.zeros((30, 40), bool)
+    holes[14:16, 19:21] = True
+    fr = plane_frame(d, holes=holes)
+    a, b = maps(s, tau)
+    fuse(a, [fr], [np.eye(4)])
+    fuse(b, [fr], [np.eye(4)])
+    # a voxel in front of the hole, half-way to the wall
+    y = np.array([0.0, 0.0, 0.6])
+    ok_a, _ = a.sample(y)
+    ok_b, out = b.sample(y)
+    assert not ok_a            # per-voxel carving left voxels in front of the hole unobserved
+    assert ok_b and out[0] == float(np.float32(tau))
+    # the same frame with the hole masked instead: nothing is carved whole there
+    mask = holes.astype(np.uint8)
+    _, c = maps(s, tau)
+    fuse(c, [plane_frame(d)], [np.eye(4)], masks=[mask])
+    ok_c, _ = c.sample(y)
+    assert not ok_c
+
+
+def test_clipping_plane_and_image_border_keep_per_voxel_rule():
+    """Blocks reaching past the clipping plane or out of the image are never
+    carved whole: with the wall beyond the clipping plane (1.0 m) the
+    compact map keeps no free block past 1.0 m - tau."""
+    s, tau = 0.02, 0.06
+    _, b = maps(s, tau, dmax=1.0)
+    fuse(b, [plane_frame(1.8)] * 2, [np.eye(4)] * 2)
+    fk, fw = b.export_free()
+    zmax = A.block_voxel_centres(fk, s)[:, :, 2].max(1)
+    assert len(fk) > 10 and np.all(zmax + 1e-3 <= 1.0)
+    c = A.block_voxel_centres(fk, s).reshape(-1, 3)
+    u = 30 * c[:, 0] / c[:, 2] + 19.5
+    v = 30 * c[:, 1] / c[:, 2] + 14.5
+    assert np.all((u >= 0.5) & (u <= 38.5) & (v >= 0.5) & (v <= 28.5))
+
+
+def test_free_block_becomes_voxels_starting_from_its_value():
+    """Free blocks in front of a wall at 1.6 m (3 frames), then a wall at
+    1.2 m: the blocks the new wall cuts become voxel blocks whose voxels start
+    from (tau, 3), so a band voxel holds (3 tau + (d - z)) / 4 and weight 4."""
+    s, tau = 0.02, 0.06
+    _, b = maps(s, tau)
+    fuse(b, [plane_frame(1.6)] * 3, [np.eye(4)] * 3)
+    fk3, fw3 = b.export_free()
+    free3 = {tuple(k) for k in fk3}
+    assert np.all(fw3 == 3)
+    fuse(b, [plane_frame(1.2)], [np.eye(4)])
+    keys, sdf, w, _ = b.export()
+    cen = A.block_voxel_centres(keys, s)
+    D, T = float(np.float32(1.2)), float(np.float32(tau))
+    checked = 0
+    for i, k in enumerate(map(tuple, keys)):
+        if k not in free3:
+            continue
+        c = cen[i]
+        band = (np.abs(D - c[:, 2]) < tau - 1e-6) & (w[i] == 4)
+        ref = (3 * T + (D - c[:, 2])) / 4
+        np.testing.assert_allclose(sdf[i][band], ref[band], rtol=0, atol=1e-15)
+        checked += band.sum()
+    assert checked > 50
