@@ -24,7 +24,9 @@ sweep): its algorithmic bytes come from the host footprint of sampled frames
 "roofline_integrate" is the integration kernel, whose algorithmic bytes come
 from device counters of voxel updates.  Extra measurements after the
 headline: the same sequence in FP16+u8 storage ("fp16", with its final pose
-against FP32's), with the clipping plane at 5 m ("depth_max_5m"), and the
+against FP32's), with compact free space ("compact": blocks carved whole,
+free blocks without voxels; its final pose against the per-voxel map's and
+its voxel memory), with the clipping plane at 5 m ("depth_max_5m"), and the
 640x480 static room of 300 frames at 1 cm voxels ("static_room").  The CPU
 oracle is timed on a bounded sample of the headline sequence, single-thread
 and with all host cores ("cpu_baseline").
@@ -275,7 +277,7 @@ def h2d_measurement(seq, frames, ks, dev):
     return float(np.median(ms)), int(dh.numel() * dh.element_size() + ch.numel())
 
 
-def run_workload(seq, frames, storage, W, K, B, dev, name, depth_max=None):
+def run_workload(seq, frames, storage, W, K, B, dev, name, depth_max=None, free_blocks=False):
     """Fuses the sequence with the full method per frame; frames 0 .. n-K-W-1
     build the map untimed, the next W are warmup, the last K are timed.
     Returns the measurement dict (frames/s, latencies, stages, rooflines)."""
@@ -290,7 +292,7 @@ def run_workload(seq, frames, storage, W, K, B, dev, name, depth_max=None):
         raise SystemExit("%s: --steps + --warmup must leave frame 0 before them (%d frames)" % (name, n_run))
     dmax = seq.depth_max if depth_max is None else depth_max
     mp = rf.MapParams(seq.voxel_size, seq.truncation, dmax, seq.num_buckets, WORKLOAD_BLOCKS[seq.name], 255,
-                      seq.carve_stride, storage, seq.width * seq.height)
+                      seq.carve_stride, storage, seq.width * seq.height, free_blocks)
     tp = rf.TrackParams(seq.levels, seq.iters, 0.025, 64, 0.0)
     mk = rf.MaskParams(0.5, 0.007)
     sessions = [rf.Session(mp, seq.poses[offset * i], dev) for i in range(B)]
@@ -349,7 +351,7 @@ def run_workload(seq, frames, storage, W, K, B, dev, name, depth_max=None):
     alg_per_launch = alg_bytes / K                          # one integration launch per step
     integ_ms = float(per_stage[:, 4].mean())
     achieved = alg_per_launch / (integ_ms * 1e-3) / 1e9
-    key = profile_key(seq.name, n_run, storage, dmax, K) if B == 1 else None
+    key = profile_key(seq.name, n_run, storage, dmax, K) if B == 1 and not free_blocks else None
     traffic, l2_hit = traffic_from_profile("integrate_kernel", key) if key else (None, None)
     track_traffic, track_l2_hit = traffic_from_profile("track_kernel", key) if key else (None, None)
 
@@ -376,6 +378,11 @@ def run_workload(seq, frames, storage, W, K, B, dev, name, depth_max=None):
         "map": {"blocks": nblocks, "flags": flags, "final_position_error_m": round(float(np.linalg.norm(E[:3, 3])), 5)},
         "profile_key": key,
     }
+    out["roofline_integrate"]["blocks_carved_whole_per_launch"] = int((c1[4] - c0[4]) / K)
+    if free_blocks:
+        keys_total = sessions[0].map.num_keys()
+        out["map"].update({"blocks_with_voxels": nblocks, "free_blocks": keys_total - nblocks,
+                           "voxel_bytes": int(nblocks) * 512 * ({"fp32": 12, "fp16": 8}[storage])})
     return out, sessions
 
 
@@ -453,10 +460,10 @@ def main():
     ap.add_argument("--storage", default=None, choices=["fp32", "fp16"],
                     help="voxel storage (default fp32; serving default fp16)")
     ap.add_argument("--depth-max", type=float, default=None, help="clipping plane (default: the workload's)")
-    ap.add_argument("--extras", default="fp16,depth_max_5m,static_room",
+    ap.add_argument("--extras", default="fp16,compact,depth_max_5m,static_room",
                     help="comma list of extra measurements after the headline: fp16 (same sequence, FP16+u8 "
-                         "storage), depth_max_5m (same sequence, clipping plane 5 m), static_room (300 frames), "
-                         "or none")
+                         "storage), compact (same sequence, compact free space), depth_max_5m (same sequence, "
+                         "clipping plane 5 m), static_room (300 frames), or none")
     ap.add_argument("--sessions", type=int, default=64, help="serving: concurrent sessions")
     ap.add_argument("--serve-scale", type=float, default=1.0, help="serving: scale of session lengths")
     ap.add_argument("--serve-src-frames", type=int, default=40, help="serving: rendered frames per source")
@@ -495,7 +502,7 @@ def main():
     if not 1 <= B <= 8:
         raise SystemExit("--batch must be in [1, 8]")
     extras = [] if args.extras in ("", "none") else args.extras.split(",")
-    order = ("fp16", "depth_max_5m", "static_room")  # static_room last: it replaces the uploaded frames
+    order = ("fp16", "compact", "depth_max_5m", "static_room")  # static_room last: it replaces the frames
     for e in extras:
         if e not in order:
             raise SystemExit("unknown extra %s" % e)
@@ -549,6 +556,14 @@ def main():
                                            "dr_rad": round(float(np.arccos(np.clip((np.trace(dT[:3, :3]) - 1) / 2,
                                                                                    -1, 1))), 8)}
                 out["fp16"] = r
+            elif e == "compact":
+                r, ss = run_workload(seq, frames, storage, W, K, 1, dev, "compact", args.depth_max, free_blocks=True)
+                Tc = ss[0].pose.cpu().numpy()
+                dT = np.linalg.inv(pose_head) @ Tc
+                r["final_pose_vs_per_voxel"] = {"dt_m": round(float(np.linalg.norm(dT[:3, 3])), 7),
+                                                "dr_rad": round(float(np.arccos(np.clip((np.trace(dT[:3, :3]) - 1) / 2,
+                                                                                        -1, 1))), 8)}
+                out["compact"] = r
             elif e == "depth_max_5m" and (args.depth_max or seq.depth_max) != 5.0:
                 r, ss = run_workload(seq, frames, storage, W, K, 1, dev, "depth_max_5m", 5.0)
                 out["depth_max_5m"] = r

@@ -87,6 +87,13 @@ typedef struct {
   uint32_t carve_stride;  /* pixels (u,v) with u,v = 0 mod stride cast carve rays from the camera */
   int32_t storage;        /* RF_STORAGE_FP32 | RF_STORAGE_FP16_U8 */
   uint32_t max_pixels;    /* largest width*height passed to compute_dynamic_mask */
+  int32_t free_blocks;    /* 1: compact free space (the free-space representation Sec. III-D leaves to
+                             future work, as coarse free-block flags): a listed block whose image
+                             rectangle holds only depths beyond it (+tau) is carved whole; a block only
+                             ever carved whole keeps no voxels, its 512 voxels read as (sdf tau,
+                             weight = frames that carved it, colour 0), and it takes a pool slot the
+                             first time a frame does not carve it whole.  Needs num_buckets <= 2^22.
+                             0: every voxel carved by the per-voxel rule (Sec. III-D as written). */
 } rf_map_params;
 
 typedef struct {
@@ -261,12 +268,25 @@ rf_status map_status(rf_map* m, void* stream, uint32_t* flags, uint32_t* n_block
  * *d_count (device uint32) = list length. */
 rf_status hashmap_frame_blocks(rf_map* m, int32_t* d_keys, uint32_t cap, uint32_t* d_count, void* stream);
 
-/* Export of every allocated block (checkpoint): d_keys int32 cap x 3,
- * d_sdf float32 cap x 512 (metres, decoded), d_weight float32 cap x 512,
- * d_rgb uint8 cap x 512 x 3 (each device, nullable); *d_count (device) =
- * number of blocks (order arbitrary; only cap are written). */
+/* Export of every allocated block that holds voxels (checkpoint): d_keys
+ * int32 cap x 3, d_sdf float32 cap x 512 (metres, decoded), d_weight float32
+ * cap x 512, d_rgb uint8 cap x 512 x 3 (each device, nullable); *d_count
+ * (device) = number of blocks (order arbitrary; only cap are written).  The
+ * free blocks of a compact free-space map hold no voxels and are exported by
+ * hashmap_export_free. */
 rf_status hashmap_export(rf_map* m, int32_t* d_keys, float* d_sdf, float* d_weight, uint8_t* d_rgb,
                          uint32_t cap, uint32_t* d_count, void* stream);
+
+/* Free blocks of a compact free-space map (rf_map_params.free_blocks = 1;
+ * the free-space representation Sec. III-D leaves to future work): d_keys
+ * (device int32, cap x 3 block coordinates), d_weight (device float32 cap,
+ * nullable) = the weight all 512 voxels of the block read as (their sdf
+ * reads as the truncation; 0 = not yet observed).  *d_count (device uint32)
+ * = number of free blocks; order arbitrary, and when it exceeds cap, which
+ * cap of them are written is unspecified.  A map without compact free space
+ * has none. */
+rf_status hashmap_export_free(rf_map* m, int32_t* d_keys, float* d_weight, uint32_t cap, uint32_t* d_count,
+                              void* stream);
 
 /* Import of n blocks in hashmap_export's layout (device arrays; keys must be
  * distinct).  Existing blocks with the same key are overwritten.  FP16

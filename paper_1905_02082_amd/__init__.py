@@ -70,11 +70,12 @@ class MapParams:
     carve_stride: int = 4
     storage: str = "fp32"            # "fp32" | "fp16"
     max_pixels: int = 640 * 480
+    free_blocks: bool = False        # compact free space (blocks carved whole, free blocks without voxels)
 
     def c(self):
         st = {"fp32": N.RF_STORAGE_FP32, "fp16": N.RF_STORAGE_FP16_U8}[self.storage]
         return N.RfMapParams(self.voxel_size, self.truncation, self.depth_max, self.num_buckets, self.max_blocks,
-                             self.max_weight, self.carve_stride, st, self.max_pixels)
+                             self.max_weight, self.carve_stride, st, self.max_pixels, 1 if self.free_blocks else 0)
 
 
 @dataclasses.dataclass
@@ -307,9 +308,21 @@ class Map:
             return self.mesh(cap=n, stream=stream)
         return tris[:n]
 
+    def export_free(self, stream=None):
+        """Compact free space: (keys (n,3) int32, weights (n,) float32) of the
+        free blocks, on the device, in no particular order."""
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(self.L.hashmap_export_free(self.h, None, None, 0, _ptr(cnt), _stream(stream)), "hashmap_export_free")
+        n = int(cnt.item())
+        keys = torch.empty((max(n, 1), 3), dtype=torch.int32, device=self.device)
+        w = torch.empty(max(n, 1), dtype=torch.float32, device=self.device)
+        _check(self.L.hashmap_export_free(self.h, _ptr(keys), _ptr(w), n, _ptr(cnt), _stream(stream)),
+               "hashmap_export_free")
+        return keys[:n], w[:n]
+
     def _state_words(self):
         off = (-self.arena.data_ptr()) % 256
-        return self.arena[off:off + 80].clone().cpu().view(torch.int64)
+        return self.arena[off:off + 88].clone().cpu().view(torch.int64)
 
     def stats_counts(self):
         """(band, free) voxel updates of the last integration (device state)."""
@@ -318,9 +331,14 @@ class Map:
 
     def cumulative_counts(self):
         """Since creation: (band updates, free-space updates, listed blocks
-        integrated, integrations)."""
+        integrated, integrations, listed blocks carved whole)."""
         v = self._state_words()
-        return tuple(int(v[i].item()) for i in range(6, 10))
+        return tuple(int(v[i].item()) for i in range(6, 11))
+
+    def num_keys(self):
+        """Blocks in the hash table (with compact free space: free blocks too)."""
+        v = self._state_words()
+        return int(v[3].item()) >> 32
 
 
 class Session:

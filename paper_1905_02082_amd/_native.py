@@ -34,7 +34,8 @@ class RfFrame(ctypes.Structure):
 class RfMapParams(ctypes.Structure):
     _fields_ = [("voxel_size", c_float), ("truncation", c_float), ("depth_max", c_float),
                 ("num_buckets", c_uint32), ("max_blocks", c_uint32), ("max_weight", c_uint32),
-                ("carve_stride", c_uint32), ("storage", c_int32), ("max_pixels", c_uint32)]
+                ("carve_stride", c_uint32), ("storage", c_int32), ("max_pixels", c_uint32),
+                ("free_blocks", c_int32)]
 
 
 class RfTrackParams(ctypes.Structure):
@@ -79,6 +80,7 @@ EXPORTS = {
     "extract_mesh": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "raycast_depth": (c_int32, [c_void_p, c_void_p, c_void_p, c_float, c_float, c_float, c_int32, c_void_p,
                                 c_void_p]),
+    "hashmap_export_free": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "map_status": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_uint32), ctypes.POINTER(c_uint32)]),
     "hashmap_frame_blocks": (c_int32, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "hashmap_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p,

@@ -36,8 +36,8 @@ rf_status check_launch(const char* what) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, mesh, total;
-  uint32_t dirty_cap, tc_tiles;
+  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, mesh, cells, total;
+  uint32_t dirty_cap, tc_tiles, cells_cap;
 };
 
 bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
@@ -53,6 +53,9 @@ rf_status validate_params(const rf_map_params* p) {
   if (p->carve_stride < 1) return fail(RF_EINVAL, "carve_stride must be >= 1");
   if (p->storage != RF_STORAGE_FP32 && p->storage != RF_STORAGE_FP16_U8) return fail(RF_EINVAL, "unknown storage");
   if (p->max_pixels > (1u << 26)) return fail(RF_EINVAL, "max_pixels too large");
+  if (p->free_blocks != 0 && p->free_blocks != 1) return fail(RF_EINVAL, "free_blocks must be 0 or 1");
+  if (p->free_blocks && p->num_buckets > (1u << 22))
+    return fail(RF_EINVAL, "compact free space needs num_buckets <= 2^22");
   return RF_OK;
 }
 
@@ -68,7 +71,7 @@ Layout layout_of(const rf_map_params* p) {
   L.rgb = o; o = align256(o + (size_t)p->max_blocks * 512 * 4);
   L.partials = o; o = align256(o + (size_t)rf::kTrackScratchWords * 8);
   L.md = o; o = align256(o + (size_t)p->max_pixels);
-  L.counts = o; o = align256(o + (size_t)rf::kIntegGroups * 8);
+  L.counts = o; o = align256(o + (size_t)rf::kIntegGroups * 16);
   L.dirty_cap = p->max_pixels / 16 + 64;
   L.dirty = o; o = align256(o + (size_t)L.dirty_cap * 2 * 4);  // two flag buffers
   // tracking block cache: the 16x16 tiles of a max_pixels frame plus slack
@@ -77,6 +80,10 @@ Layout layout_of(const rf_map_params* p) {
   L.tcache = o; o = align256(o + (size_t)rf::tile_refs_before(rf::kCacheLevels) * L.tc_tiles * sizeof(rf::BlockRef));
   L.tc_count = o; o = align256(o + (size_t)rf::kCacheLevels * L.tc_tiles * 4);
   L.mesh = o; o = align256(o + (size_t)2 * rf::kMeshScratch * 4);
+  // compact free space: the 8x8 depth cells of a frame of up to max_pixels
+  // pixels; ceil(W/8) ceil(H/8) <= W H / 64 + (W + H) / 8 + 1
+  L.cells_cap = p->free_blocks ? p->max_pixels / 64 + (p->max_pixels + 1) / 8 + 2 : 0;
+  L.cells = o; o = align256(o + (size_t)L.cells_cap * 4);
   L.total = o;
   return L;
 }
@@ -244,7 +251,10 @@ rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void
   d.rgb = reinterpret_cast<uchar4*>(a + L.rgb);
   d.partials = reinterpret_cast<double*>(a + L.partials);
   d.md = reinterpret_cast<uint8_t*>(a + L.md);
-  d.integ_counts = reinterpret_cast<uint2*>(a + L.counts);
+  d.integ_counts = reinterpret_cast<uint4*>(a + L.counts);
+  d.cells = reinterpret_cast<float*>(a + L.cells);
+  d.cells_cap = L.cells_cap;
+  d.free_blocks = p->free_blocks ? 1u : 0u;
   d.dirty = reinterpret_cast<uint32_t*>(a + L.dirty);
   d.tcache = reinterpret_cast<rf::BlockRef*>(a + L.tcache);
   d.tc_count = reinterpret_cast<uint32_t*>(a + L.tc_count);
@@ -418,6 +428,16 @@ rf_status integrate_frame_batch(const rf_job* jobs, int32_t n, void* stream) {
   auto fill = [&](const rf_job& j, rf::Job& J) -> rf_status {
     J.pose = j.d_pose;
     J.mask = j.d_mask;
+    J.cells_w = J.cells_h = 0;
+    if (J.m.free_blocks) {
+      // compact free space: the frame's depth cells must fit the map's
+      const uint32_t npx = (uint32_t)J.f.W * (uint32_t)J.f.H;
+      if (npx > j.map->h.p.max_pixels)
+        return fail(RF_ENOMEM, "integrate_frame: frame has %u pixels, map max_pixels is %u", npx,
+                    j.map->h.p.max_pixels);
+      J.cells_w = (J.f.W + rf::kCell - 1) / rf::kCell;
+      J.cells_h = (J.f.H + rf::kCell - 1) / rf::kCell;
+    }
     return RF_OK;
   };
   auto launch = [&](rf::Batch& b, int df, int sto) { rf::launch_integrate(b, df, sto, S(stream)); };
@@ -489,6 +509,13 @@ rf_status hashmap_frame_blocks(rf_map* m, int32_t* d_keys, uint32_t cap, uint32_
   if (!m || !d_count || (cap && !d_keys)) return fail(RF_EINVAL, "map/count/keys is NULL");
   rf::launch_frame_blocks(m->h.dev, d_keys, cap, d_count, S(stream));
   return check_launch("hashmap_frame_blocks");
+}
+
+rf_status hashmap_export_free(rf_map* m, int32_t* d_keys, float* d_weight, uint32_t cap, uint32_t* d_count,
+                              void* stream) {
+  if (!m || !d_count || (cap && !d_keys)) return fail(RF_EINVAL, "map/count/keys is NULL");
+  rf::launch_export_free(m->h.dev, m->h.p.num_buckets, d_keys, d_weight, cap, d_count, S(stream));
+  return check_launch("hashmap_export_free");
 }
 
 rf_status hashmap_export(rf_map* m, int32_t* d_keys, float* d_sdf, float* d_weight, uint8_t* d_rgb, uint32_t cap,

@@ -12,6 +12,7 @@
 //   tile refs    tracking block cache: per level l < kCacheLevels, tc_tiles x tile_refs(l) x 16 B {key, slot, epoch},
 //                then kCacheLevels x tc_tiles x 4 B pair counts
 //   mesh scratch 2 x kMeshScratch x 4 B
+//   cells        compact free space only: per 8x8 pixel cell of the frame, its smallest measured depth
 //
 // Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
 // linear probing, insertion by 64-bit CAS on the key word (insert-only: keys
@@ -29,6 +30,13 @@ namespace rf {
 
 constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr uint32_t kInvalidSlot = 0xFFFFFFFFu;
+// Compact free space: a bucket of a free block holds kFreeSlot | c instead of
+// a pool slot, c = frames that carved it whole (capped at the weight cap).
+constexpr uint32_t kFreeSlot = 0x80000000u;
+__host__ __device__ __forceinline__ bool is_free_slot(uint32_t s) { return (s & 0xFFFFFF00u) == kFreeSlot; }
+// Slot codes returned by resolve_slot: >= 0 pool slot, -1 absent (or no pool
+// slot), <= -2 free block with count -2 - code.
+__host__ __device__ __forceinline__ int free_code(uint32_t s) { return -2 - (int)(s & 0xFFu); }
 constexpr int kKeyBias = 1 << 20;
 constexpr float kMaxBlockCoord = 1.0e6f;   // |block coordinate| limit (key range 2^20)
 constexpr float kMaxVoxelCoord = 8.0e6f;   // |voxel coordinate| limit (8 x 2^20 > 8e6)
@@ -45,6 +53,7 @@ constexpr int kTrackScratchWords = 3 * kAccCopies * 29 * 16 + 32 + 2 * 48;
 constexpr int kIntegGroups = 1536;  // integration workgroups per launch (all jobs together)
 constexpr int kNE = 29;                    // 21 H + 6 g + cost + count
 constexpr int kTile = 32;                  // flood-fill tile edge
+constexpr int kCell = 8;                   // compact free space: depth-cell edge (pixels)
 
 // Tracking block cache: for every pyramid level below kCacheLevels and every
 // tracking tile, the (block key, pool slot) pairs its pixels looked up in the
@@ -83,13 +92,14 @@ struct DevState {
   uint32_t track_stop;     // 1: the running registration pass stopped (degenerate)
   uint32_t dirty_count;    // flood fill: tiles marked since the last sweep
   uint32_t epoch;          // allocation epoch (frame stamps in the buckets), advanced on the device
-  uint32_t pad;
+  uint32_t n_keys;         // blocks inserted into the hash (with compact free space: free blocks too)
   unsigned long long n_band;  // voxels updated in the band by the last integration
   unsigned long long n_free;  // voxels carved by the last integration
   unsigned long long cum_band;    // since create/reset: band updates
   unsigned long long cum_free;    // since create/reset: free-space updates
   unsigned long long cum_blocks;  // since create/reset: listed blocks integrated
   unsigned long long cum_frames;  // since create/reset: integrations
+  unsigned long long cum_whole;   // since create/reset: listed blocks carved whole (compact free space)
 };
 
 // Starts a new allocation epoch: 0 is the stamp of a bucket never touched,
@@ -112,7 +122,11 @@ struct MapDev {
   DevState* st;
   double* partials;
   uint8_t* md;
-  uint2* integ_counts;  // per integration workgroup: (band, free) updates of the last integration
+  uint4* integ_counts;  // per integration workgroup: (band, free, blocks carved whole, 0) of the last integration
+  float* cells;         // compact free space: per 8x8 pixel cell of the frame being integrated, the
+                        // smallest measured depth (0 if a pixel is masked or none is measured)
+  uint32_t cells_cap;
+  uint32_t free_blocks; // 1: compact free space
   BlockRef* tcache;     // tracking block cache (per level: tc_tiles tiles of tile_refs(level) pairs)
   uint32_t* tc_count;   // valid pairs of each cached tile (kCacheLevels x tc_tiles)
   uint32_t* mesh_scratch;  // mesh extraction: triangles and offsets per workgroup (2 x kMeshScratch)
@@ -155,7 +169,9 @@ __device__ __forceinline__ uint32_t hash3(int x, int y, int z) {
   return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u);
 }
 
-// Pool slot of block (x,y,z) or -1 (absent, or no slot because the pool was full).
+// Pool slot of block (x,y,z) or -1 (absent, a free block, or no slot because
+// the pool was full).  Free blocks read as absent here: every voxel of one
+// holds sdf = tau, which no zero-crossing test accepts.
 __device__ __forceinline__ int find_slot(const MapDev& m, int x, int y, int z) {
   const unsigned long long key = pack_key(x, y, z);
   uint32_t h = hash3(x, y, z) & m.bucket_mask;
@@ -168,11 +184,12 @@ __device__ __forceinline__ int find_slot(const MapDev& m, int x, int y, int z) {
   return -1;
 }
 
-// Slot of the key given the bucket b read at index h (its home bucket):
-// continues the linear probe only when b holds another key.
+// Slot code of the key given the bucket b read at index h (its home bucket):
+// continues the linear probe only when b holds another key.  >= 0 pool slot,
+// -1 absent (or no pool slot), <= -2 free block (free_code).
 __device__ __forceinline__ int resolve_slot(const MapDev& m, Bucket b, unsigned long long key, uint32_t h) {
   for (uint32_t i = 1;; ++i) {
-    if (b.key == key) return (b.slot < m.max_blocks) ? (int)b.slot : -1;
+    if (b.key == key) return (b.slot < m.max_blocks) ? (int)b.slot : (is_free_slot(b.slot) ? free_code(b.slot) : -1);
     if (b.key == kEmptyKey || i >= m.max_probe) return -1;
     h = (h + 1) & m.bucket_mask;
     b = m.buckets[h];
@@ -189,12 +206,18 @@ __device__ __forceinline__ int insert_block(const MapDev& m, int x, int y, int z
     if (k == kEmptyKey) {
       unsigned long long old = atomicCAS(&m.buckets[h].key, kEmptyKey, key);
       if (old == kEmptyKey) {
-        uint32_t slot = atomicAdd(&m.st->n_blocks, 1u);
-        if (slot < m.max_blocks) {
-          m.block_keys[slot] = key;
+        atomicAdd(&m.st->n_keys, 1u);
+        uint32_t slot;
+        if (m.free_blocks) {
+          slot = kFreeSlot;  // a free block: no voxels until a frame does not carve it whole
         } else {
-          slot = kInvalidSlot;
-          atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
+          slot = atomicAdd(&m.st->n_blocks, 1u);
+          if (slot < m.max_blocks) {
+            m.block_keys[slot] = key;
+          } else {
+            slot = kInvalidSlot;
+            atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
+          }
         }
         m.buckets[h].slot = slot;
         return (int)h;
@@ -335,7 +358,7 @@ struct HashSlots {
       b0.key = bkey[k];
       b0.slot = bslot[k];
       sl[k] = resolve_slot(m, b0, pack_key(x, y, z), hash3(x, y, z) & m.bucket_mask);
-      if (sl[k] < 0) return false;
+      if (sl[k] == -1) return false;
     }
     return true;
   }
@@ -355,14 +378,16 @@ __device__ __forceinline__ bool voxel_cell(const MapDev& m, const float y[3], in
   return true;
 }
 
-// The 8 corner records (and colours) of cell i0.  `slots` finds the pool
-// slots of the corner blocks (HashSlots: the hash table; tracking adds a
-// per-tile cache in front of it); false if a corner block is absent.  All
-// loads are issued before any is used, so they share one round trip.  With
-// PIN the empty asm statements pin every loaded value here: without them the
-// compiler sinks each load into the branch that first uses it, which turns
-// the gathers back into a chain of round trips.  Without PIN the loads stay
-// in flight for a later use (a speculative gather).
+// The 8 corner records (and colours) of cell i0.  `slots` finds the slot
+// codes of the corner blocks (HashSlots: the hash table; tracking adds a
+// per-tile cache in front of it); false if a corner block is absent.  A
+// corner in a free block (compact free space) reads (tau, count, colour 0),
+// or unobserved while its count is 0.  All loads are issued before any is
+// used, so they share one round trip.  With PIN the empty asm statements pin
+// every loaded value here: without them the compiler sinks each load into the
+// branch that first uses it, which turns the gathers back into a chain of
+// round trips.  Without PIN the loads stay in flight for a later use (a
+// speculative gather).
 template <int STORAGE, bool WANT_COLOUR, bool PIN, class Slots>
 __device__ __forceinline__ bool gather_corners(const MapDev& m, const int i0[3], const Slots& slots, float cs[8],
                                                float cw[8], uint32_t cc[8]) {
@@ -373,8 +398,8 @@ __device__ __forceinline__ bool gather_corners(const MapDev& m, const int i0[3],
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-    const uint32_t idx = (uint32_t)sl[k] * 512u + (uint32_t)(((i0[0] + dx) & 7) + 8 * ((i0[1] + dy) & 7) +
-                                                             64 * ((i0[2] + dz) & 7));
+    const uint32_t idx = (uint32_t)(sl[k] >= 0 ? sl[k] : 0) * 512u +
+                         (uint32_t)(((i0[0] + dx) & 7) + 8 * ((i0[1] + dy) & 7) + 64 * ((i0[2] + dz) & 7));
     VoxelStore<STORAGE>::load(m, idx, cs[k], cw[k]);
     if (WANT_COLOUR) cc[k] = reinterpret_cast<const uint32_t*>(m.rgb)[idx];
   }
@@ -384,6 +409,14 @@ __device__ __forceinline__ bool gather_corners(const MapDev& m, const int i0[3],
       asm volatile("" : "+v"(cs[k]), "+v"(cw[k]));
       if (WANT_COLOUR) asm volatile("" : "+v"(cc[k]));
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (sl[k] >= 0) continue;  // free block
+    const float c = (float)(-2 - sl[k]);
+    cs[k] = c > 0.0f ? m.tau : 0.0f;
+    cw[k] = c;
+    if (WANT_COLOUR) cc[k] = 0u;
   }
   return true;
 }

@@ -264,6 +264,134 @@ __global__ void reset_frame_list_kernel(Batch b) {
   }
 }
 
+// ------------------------------------------------ compact free space
+// (maps with free_blocks = 1; the free-space representation Sec. III-D
+// leaves to future work, as coarse free-block flags.)  Before the
+// integration every listed block is tested for being carved whole: its 8
+// corner voxels, transformed as the integration transforms voxels, lie more
+// than 1 mm in front of the camera and at least 1 mm before the clipping
+// plane, the nearest pixels of their projections widened by one pixel span a
+// rectangle inside the image of at most 64 depth cells (8x8 pixels), and
+// every one of those cells holds a depth more than tau + 1 mm beyond the
+// block's farthest corner (a cell: the smallest depth of its measured
+// pixels; 0, failing the test, when a pixel is masked or none is measured).
+// The voxels' depths and projections lie within the corners' range, far
+// inside the margins, so with every pixel measured the per-voxel rule would
+// carve every voxel of such a block; unmeasured pixels are carved over.
+//
+// A free block (no voxels, bucket slot kFreeSlot | count) carved whole only
+// counts the frame.  A free block not carved whole takes a pool slot here and
+// is integrated voxel by voxel from its value (tau and its count, or
+// unobserved while the count is 0).  A block of voxels carved whole gives
+// every voxel the free-space update without projecting it.  The outcome of
+// each listed block goes into bits 22-31 of its frame-list entry (bucket
+// indices stay below 2^22).
+constexpr uint32_t kEntryBucket = 0x003FFFFFu;
+constexpr uint32_t kEntryWhole = 0x80000000u;  // carved whole
+constexpr uint32_t kEntryFresh = 0x40000000u;  // pool slot taken now: voxels start from (tau, count)
+constexpr int kEntryCountShift = 22;           // the free block's count (bits 22-29) of a fresh block
+constexpr float kCarveMargin = 1.0e-3f;        // metres
+constexpr int kMaxTestCells = 64;
+constexpr int kClassifyGroups = 512;           // workgroups of the whole-block test (all jobs together)
+
+template <int DF>
+__global__ __launch_bounds__(256) void depth_cells_kernel(Batch b) {
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const FrameDev& f = J.f;
+  const int c = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
+  if (c >= J.cells_w * J.cells_h) return;
+  const int u0 = (c % J.cells_w) * kCell, v0 = (c / J.cells_w) * kCell;
+  const uint8_t* mask = J.mask;
+  float e = INFINITY;
+  bool masked = false;
+  for (int dv = 0; dv < kCell; ++dv) {
+    const int v = v0 + dv;
+    if (v >= f.H) break;
+    for (int du = 0; du < kCell; ++du) {
+      const int u = u0 + du;
+      if (u >= f.W) break;
+      const int idx = v * f.W + u;
+      const float D = load_depth<DF>(f, idx);
+      masked = masked || (mask && mask[idx]);
+      if (D > 0.0f) e = fminf(e, D);
+    }
+  }
+  J.m.cells[c] = (masked || e == INFINITY) ? 0.0f : e;
+}
+
+__device__ __forceinline__ bool carved_whole(const MapDev& m, const FrameDev& f, const Job& J, const float R[9],
+                                             const float t[3], int bx, int by, int bz) {
+  if (J.cells_w <= 0) return false;
+  float zmin = INFINITY, zmax = -INFINITY, umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float d0 = (float)(8 * bx + ((k & 1) ? 7 : 0)) * m.s - t[0];
+    const float d1 = (float)(8 * by + ((k & 2) ? 7 : 0)) * m.s - t[1];
+    const float d2 = (float)(8 * bz + ((k & 4) ? 7 : 0)) * m.s - t[2];
+    const float x0 = (R[0] * d0 + R[3] * d1) + R[6] * d2;
+    const float x1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
+    const float x2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
+    zmin = fminf(zmin, x2);
+    zmax = fmaxf(zmax, x2);
+    const float zz = fmaxf(x2, kCarveMargin);
+    const float uf = f.fx * (x0 / zz) + f.cx, vf = f.fy * (x1 / zz) + f.cy;
+    umin = fminf(umin, uf);
+    umax = fmaxf(umax, uf);
+    vmin = fminf(vmin, vf);
+    vmax = fmaxf(vmax, vf);
+  }
+  if (!(zmin > kCarveMargin && zmax + kCarveMargin <= m.dmax)) return false;
+  const float u0 = floorf(umin + 0.5f) - 1.0f, u1 = floorf(umax + 0.5f) + 1.0f;
+  const float v0 = floorf(vmin + 0.5f) - 1.0f, v1 = floorf(vmax + 0.5f) + 1.0f;
+  if (!(u0 >= 0.0f && v0 >= 0.0f && u1 <= (float)(f.W - 1) && v1 <= (float)(f.H - 1))) return false;
+  const int c0 = (int)u0 / kCell, c1 = (int)u1 / kCell, r0 = (int)v0 / kCell, r1 = (int)v1 / kCell;
+  if ((c1 - c0 + 1) * (r1 - r0 + 1) > kMaxTestCells) return false;
+  float dmin = INFINITY;
+  for (int r = r0; r <= r1; ++r)
+    for (int c = c0; c <= c1; ++c) dmin = fminf(dmin, m.cells[r * J.cells_w + c]);
+  return dmin > zmax + m.tau + kCarveMargin;
+}
+
+__global__ __launch_bounds__(256) void classify_kernel(Batch b) {
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  if (!m.free_blocks) return;
+  const FrameDev& f = J.f;
+  const uint32_t nF = min(m.st->f_count, m.flist_cap);
+  const uint32_t g0 = blockIdx.x - b.base[jb], gn = b.base[jb + 1] - b.base[jb];
+  float R[9], t[3];
+  load_pose_f(J.pose, R, t);
+  const uint32_t wmax = (uint32_t)m.max_weight;
+  for (uint32_t i = g0 * blockDim.x + threadIdx.x; i < nF; i += gn * blockDim.x) {
+    const uint32_t e = m.flist[i] & kEntryBucket;
+    const Bucket bk = m.buckets[e];
+    int bx, by, bz;
+    unpack_key(bk.key, bx, by, bz);
+    const bool whole = carved_whole(m, f, J, R, t, bx, by, bz);
+    uint32_t entry = e | (whole ? kEntryWhole : 0u);
+    if (is_free_slot(bk.slot)) {
+      const uint32_t c = bk.slot & 0xFFu;
+      if (whole) {
+        m.buckets[e].slot = kFreeSlot | min(c + 1u, wmax);
+        entry |= kEntryFresh;  // whole + fresh: a free block carved whole, nothing left to do
+      } else {
+        uint32_t slot = atomicAdd(&m.st->n_blocks, 1u);
+        if (slot < m.max_blocks) {
+          m.block_keys[slot] = bk.key;
+        } else {
+          slot = kInvalidSlot;
+          atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
+        }
+        m.buckets[e].slot = slot;
+        entry |= kEntryFresh | (c << kEntryCountShift);
+      }
+    }
+    m.flist[i] = entry;
+  }
+}
+
 // Integration of one frame into the blocks of the frame list (Sec. III-A
 // running average, Sec. III-D carving).  Workgroups stride over the list and
 // take kIntegBlocks listed blocks per step; a thread owns voxels l and l + 256
@@ -287,6 +415,14 @@ __device__ __forceinline__ void take_lanes(unsigned long long key, uint32_t slot
   }
 }
 
+// Whole-block test outcome (top bits of the frame-list entry) held by the
+// wavefront's lane i.
+template <int N>
+__device__ __forceinline__ void take_state(uint32_t bits, uint32_t (&out)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = __builtin_amdgcn_readlane(bits, i);
+}
+
 template <int DF, int STORAGE>
 __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   constexpr int NV = 2 * kIntegBlocks;  // voxels per thread per step
@@ -301,7 +437,7 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   const uint32_t nF = min(m.st->f_count, m.flist_cap);
   float R[9], t[3];
   load_pose_f(J.pose, R, t);
-  uint32_t nb = 0, nf = 0;
+  uint32_t nb = 0, nf = 0, nw = 0;
   const uint32_t stride = kIntegBlocks * gn;
   // The list entries and buckets of a step are fetched during the step before
   // it (the list entries while its voxel gathers are in flight, the buckets
@@ -312,16 +448,27 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   // step starts without waiting for those stores.
   const int lane = threadIdx.x & 63;
   const uint32_t my_i = (uint32_t)min(lane, kIntegBlocks - 1);
+  // frame-list entries of compact free-space maps carry the whole-block
+  // test's outcome in their top bits (compact maps keep bucket indices below
+  // 2^22); other maps' entries are plain bucket indices
+  const uint32_t bucket_bits = m.free_blocks ? kEntryBucket : 0xFFFFFFFFu;
   Bucket cur[kIntegBlocks];
+  uint32_t cur_st[kIntegBlocks];
   if (g0 < nF) {
     const uint32_t fi = g0 + my_i * gn;
-    const Bucket bq = m.buckets[m.flist[fi < nF ? fi : g0]];
+    const uint32_t e = m.flist[fi < nF ? fi : g0];
+    const Bucket bq = m.buckets[e & bucket_bits];
     take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
+    take_state<kIntegBlocks>(e & ~bucket_bits, cur_st);
   }
   for (uint32_t f0 = g0; f0 < nF; f0 += stride) {
     Bucket bu[kIntegBlocks];
+    uint32_t st[kIntegBlocks];  // uniform: the block's whole-block test outcome
 #pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) bu[i] = cur[i];
+    for (int i = 0; i < kIntegBlocks; ++i) {
+      bu[i] = cur[i];
+      st[i] = cur_st[i];
+    }
     // the next step's list entries (past the list's end: this step's first
     // entry again, so the loads stay unconditional and in bounds)
     const uint32_t f1 = f0 + stride;
@@ -335,10 +482,18 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
     for (int v = 0; v < NV; ++v) {
       const int i = v >> 1;
       const int l = threadIdx.x + 256 * (v & 1);
-      const bool ok = f0 + i * gn < nF && bu[i].slot < m.max_blocks;
+      const bool whole = (st[i] & kEntryWhole) != 0u, fresh = (st[i] & kEntryFresh) != 0u;
+      // a free block carved whole has nothing left to update
+      const bool ok = f0 + i * gn < nF && bu[i].slot < m.max_blocks && !(whole && fresh);
+      vidx[v] = ok ? bu[i].slot * 512u + (uint32_t)l : 0u;
+      if (whole) {  // a block of voxels carved whole: no projection, no pixel
+        pix[v] = 0;
+        X2[v] = 0.0f;
+        vis[v] = ok;
+        continue;
+      }
       int bx, by, bz;
       unpack_key(bu[i].key, bx, by, bz);
-      vidx[v] = ok ? bu[i].slot * 512u + (uint32_t)l : 0u;
       // X = R^T (v s - t), summed as (R0j d0 + R1j d1) + R2j d2
       const float d0 = (float)(8 * bx + (l & 7)) * m.s - t[0];
       const float d1 = (float)(8 * by + ((l >> 3) & 7)) * m.s - t[1];
@@ -359,13 +514,26 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
     uint32_t mk[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      D[v] = load_depth<DF>(f, pix[v]);
-      mk[v] = mask_src[pix[v]];
-      VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
+      D[v] = 0.0f;
+      mk[v] = 0u;
+      if (!(st[v >> 1] & kEntryWhole)) {
+        D[v] = load_depth<DF>(f, pix[v]);
+        mk[v] = mask_src[pix[v]];
+      }
+      if (!(st[v >> 1] & kEntryFresh)) VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(D[v]), "+v"(mk[v]), "+v"(sdf[v]), "+v"(W[v]));
-    const Bucket bq = m.buckets[hn];  // the next step's buckets
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (!(st[v >> 1] & kEntryFresh)) continue;
+      // a free block that takes its pool slot now: every voxel starts from
+      // the free block's value (tau and its count; unobserved while 0)
+      const float c = (float)((st[v >> 1] >> kEntryCountShift) & 0xFFu);
+      sdf[v] = c > 0.0f ? m.tau : 0.0f;
+      W[v] = c;
+    }
+    const Bucket bq = m.buckets[hn & bucket_bits];  // the next step's buckets
     // sdf and weight of every updated voxel; the band voxels then update
     // their colour, with all colour loads of the step (the voxel's and the
     // frame's) issued together
@@ -373,22 +541,40 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       band[v] = false;
-      if (!vis[v] || !(D[v] > 0.0f) || (mask && mk[v])) continue;
-      const float eta = D[v] - X2[v];
-      if (eta < -m.tau) continue;
-      band[v] = (eta <= m.tau);
-      // the band of a measurement beyond depth_max is not integrated; the
-      // free space in front of it is carved like any other (Sec. III-D)
-      if (band[v] && !(D[v] <= m.dmax)) {
-        band[v] = false;
+      if (st[v >> 1] & kEntryWhole) {  // carved whole: the free-space update
+        if (!vis[v]) continue;
+        VoxelStore<STORAGE>::store(m, vidx[v], (W[v] * sdf[v] + m.tau) / (W[v] + 1.0f),
+                                   fminf(W[v] + 1.0f, m.max_weight));
+        nf += 1;
         continue;
       }
-      if (!band[v] && !(X2[v] <= m.dmax)) continue;
-      const float dval = band[v] ? eta : m.tau;
-      VoxelStore<STORAGE>::store(m, vidx[v], (W[v] * sdf[v] + dval) / (W[v] + 1.0f),
-                                 fminf(W[v] + 1.0f, m.max_weight));
-      nb += band[v];
-      nf += !band[v];
+      // a fresh block writes every voxel (its pool slot held nothing); the
+      // others write the voxels the frame updates
+      const int i = v >> 1;
+      const bool fresh = (st[i] & kEntryFresh) != 0u && f0 + i * gn < nF && bu[i].slot < m.max_blocks;
+      bool upd = false;
+      float dval = 0.0f;
+      if (vis[v] && D[v] > 0.0f && !(mask && mk[v])) {
+        const float eta = D[v] - X2[v];
+        if (eta >= -m.tau) {
+          const bool bnd = eta <= m.tau;
+          // the band of a measurement beyond depth_max is not integrated; the
+          // free space in front of it is carved like any other (Sec. III-D)
+          if (bnd ? (D[v] <= m.dmax) : (X2[v] <= m.dmax)) {
+            upd = true;
+            band[v] = bnd;
+            dval = bnd ? eta : m.tau;
+          }
+        }
+      }
+      if (upd) {
+        VoxelStore<STORAGE>::store(m, vidx[v], (W[v] * sdf[v] + dval) / (W[v] + 1.0f),
+                                   fminf(W[v] + 1.0f, m.max_weight));
+        nb += band[v];
+        nf += !band[v];
+      } else if (fresh) {
+        VoxelStore<STORAGE>::store(m, vidx[v], sdf[v], W[v]);
+      }
     }
     uint32_t cold[NV], cpx[NV][3];
 #pragma unroll
@@ -396,7 +582,7 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       cold[v] = 0u;
       cpx[v][0] = cpx[v][1] = cpx[v][2] = 0u;
       if (!band[v]) continue;
-      cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
+      if (!(st[v >> 1] & kEntryFresh)) cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
       const uint8_t* px = f.rgb + 3 * pix[v];
       cpx[v][0] = px[0];
       cpx[v][1] = px[1];
@@ -405,6 +591,9 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]), "+v"(cpx[v][2]));
     take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
+    take_state<kIntegBlocks>(hn & ~bucket_bits, cur_st);
+#pragma unroll
+    for (int i = 0; i < kIntegBlocks; ++i) nw += ((st[i] & kEntryWhole) && f0 + i * gn < nF) ? 1u : 0u;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if (!band[v]) continue;
@@ -425,7 +614,8 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   if (nb) atomicAdd(&s_cnt[0], nb);
   if (nf) atomicAdd(&s_cnt[1], nf);
   __syncthreads();
-  if (threadIdx.x == 0) m.integ_counts[g0] = make_uint2(s_cnt[0], s_cnt[1]);
+  // nw is uniform over the workgroup (every thread counts the same blocks)
+  if (threadIdx.x == 0) m.integ_counts[g0] = make_uint4(s_cnt[0], s_cnt[1], nw, 0u);
 }
 
 // One workgroup per job: the integration's per-workgroup counts into the
@@ -434,20 +624,23 @@ __global__ __launch_bounds__(256) void integ_fold_kernel(Batch b) {
   const Job& J = b.job[blockIdx.x];
   const MapDev& m = J.m;
   const int ng = b.base[blockIdx.x + 1] - b.base[blockIdx.x];
-  unsigned long long band = 0, free = 0;
+  unsigned long long band = 0, free = 0, whole = 0;
   for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-    const uint2 c = m.integ_counts[i];
+    const uint4 c = m.integ_counts[i];
     band += c.x;
     free += c.y;
+    whole += c.z;
   }
-  __shared__ unsigned long long s_b[256], s_f[256];
+  __shared__ unsigned long long s_b[256], s_f[256], s_w[256];
   s_b[threadIdx.x] = band;
   s_f[threadIdx.x] = free;
+  s_w[threadIdx.x] = whole;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       s_b[threadIdx.x] += s_b[threadIdx.x + w];
       s_f[threadIdx.x] += s_f[threadIdx.x + w];
+      s_w[threadIdx.x] += s_w[threadIdx.x + w];
     }
     __syncthreads();
   }
@@ -459,6 +652,10 @@ __global__ __launch_bounds__(256) void integ_fold_kernel(Batch b) {
     st->cum_free += s_f[0];
     st->cum_blocks += min(st->f_count, m.flist_cap);
     st->cum_frames += 1;
+    st->cum_whole += s_w[0];
+    // compact free space: free blocks changed their counts or took pool
+    // slots, so tracking caches must not keep their old slot codes
+    if (m.free_blocks) advance_epoch(st);
   }
 }
 
@@ -482,6 +679,26 @@ void launch_allocate(Batch& b, int depth_format, hipStream_t s) {
 }
 
 void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
+  // compact free-space maps: depth cells of the frame, then the whole-block
+  // test of every listed block (a fixed share of workgroups per job; block
+  // counts live on the device)
+  int cells = 0;
+  bool compact = false;
+  for (int j = 0; j < b.n; ++j) {
+    b.base[j] = cells;
+    cells += (b.job[j].cells_w * b.job[j].cells_h + 255) / 256;
+    compact = compact || b.job[j].m.free_blocks;
+  }
+  b.base[b.n] = cells;
+  if (compact) {
+    if (cells > 0) {
+      if (depth_format == RF_DEPTH_U16) depth_cells_kernel<RF_DEPTH_U16><<<cells, 256, 0, s>>>(b);
+      else depth_cells_kernel<RF_DEPTH_F32><<<cells, 256, 0, s>>>(b);
+    }
+    const int per_c = kClassifyGroups / b.n;
+    for (int j = 0; j <= b.n; ++j) b.base[j] = j * per_c;
+    classify_kernel<<<b.n * per_c, 256, 0, s>>>(b);
+  }
   // a fixed share of workgroups per job (block counts live on the device):
   // together one resident round (6 workgroups of 256 threads per CU)
   const int per = kIntegGroups / b.n;

@@ -33,6 +33,7 @@ struct Job {
   int tiles_x, tiles_y;     // flood-fill tile grid
   int carve_groups;         // allocation: workgroups of carve rays (before the band rays')
   int carve_w, carve_h;     // allocation: carve-grid size
+  int cells_w, cells_h;     // integration of a compact free-space map: 8x8 depth cells of the frame
 };
 
 struct Batch {
@@ -73,6 +74,8 @@ void launch_mesh(const MapDev& m, int storage, float* tris, uint32_t cap, uint32
 void launch_raycast(const MapDev& m, const FrameDev& f, int depth_format, int storage, const double* pose,
                     float z_near, float z_far, float far_value, int only_invalid, float* out, hipStream_t s);
 void launch_frame_blocks(const MapDev& m, int32_t* keys, uint32_t cap, uint32_t* count, hipStream_t s);
+void launch_export_free(const MapDev& m, uint32_t num_buckets, int32_t* keys, float* w, uint32_t cap, uint32_t* count,
+                        hipStream_t s);
 void launch_export(const MapDev& m, int storage, int32_t* keys, float* sdf, float* w, uint8_t* rgb,
                    uint32_t cap, uint32_t* count, hipStream_t s);
 void launch_import(const MapDev& m, int storage, const int32_t* keys, const float* sdf, const float* w,

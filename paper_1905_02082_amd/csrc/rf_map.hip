@@ -36,6 +36,8 @@ __global__ void init_state_kernel(DevState* st) {
     st->cum_free = 0;
     st->cum_blocks = 0;
     st->cum_frames = 0;
+    st->cum_whole = 0;
+    st->n_keys = 0;
   }
 }
 
@@ -123,7 +125,8 @@ __global__ void frame_blocks_kernel(MapDev m, int32_t* keys, uint32_t cap, uint3
   if (blockIdx.x == 0 && threadIdx.x == 0) *count = n;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n && i < cap; i += gridDim.x * blockDim.x) {
     int x, y, z;
-    unpack_key(m.buckets[m.flist[i]].key, x, y, z);
+    // compact free-space maps keep the whole-block test's outcome in bits 22-31
+    unpack_key(m.buckets[m.flist[i] & (m.free_blocks ? 0x003FFFFFu : 0xFFFFFFFFu)].key, x, y, z);
     keys[3 * i] = x;
     keys[3 * i + 1] = y;
     keys[3 * i + 2] = z;
@@ -185,6 +188,30 @@ void launch_surface(const MapDev& m, int storage, float* pts, uint32_t cap, uint
   zero_u32_kernel<<<1, 64, 0, s>>>(count);
   if (storage == RF_STORAGE_FP32) surface_kernel<RF_STORAGE_FP32><<<2048, 256, 0, s>>>(m, pts, cap, count);
   else surface_kernel<RF_STORAGE_FP16_U8><<<2048, 256, 0, s>>>(m, pts, cap, count);
+}
+
+// Free blocks of a compact free-space map: key and the weight their voxels
+// read as, in no particular order (the buckets are scanned).
+__global__ __launch_bounds__(256) void export_free_kernel(MapDev m, uint32_t num_buckets, int32_t* keys, float* w,
+                                                          uint32_t cap, uint32_t* count) {
+  for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < num_buckets; h += gridDim.x * blockDim.x) {
+    const Bucket b = m.buckets[h];
+    if (b.key == kEmptyKey || !is_free_slot(b.slot)) continue;
+    const uint32_t i = atomicAdd(count, 1u);
+    if (i >= cap) continue;
+    int x, y, z;
+    unpack_key(b.key, x, y, z);
+    keys[3 * i] = x;
+    keys[3 * i + 1] = y;
+    keys[3 * i + 2] = z;
+    if (w) w[i] = (float)(b.slot & 0xFFu);
+  }
+}
+
+void launch_export_free(const MapDev& m, uint32_t num_buckets, int32_t* keys, float* w, uint32_t cap, uint32_t* count,
+                        hipStream_t s) {
+  zero_u32_kernel<<<1, 64, 0, s>>>(count);
+  export_free_kernel<<<2048, 256, 0, s>>>(m, num_buckets, keys, w, cap, count);
 }
 
 void launch_frame_blocks(const MapDev& m, int32_t* keys, uint32_t cap, uint32_t* count, hipStream_t s) {

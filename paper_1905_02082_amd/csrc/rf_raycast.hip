@@ -19,8 +19,9 @@
 
 namespace rf {
 
-// Slots of blocks (bx + dx, by + dy, bz + dz), index dx + 2 dy + 4 dz; -1 if
-// absent.  The 8 home buckets are read together (one round trip).
+// Slot codes of blocks (bx + dx, by + dy, bz + dz), index dx + 2 dy + 4 dz;
+// -1 if absent, <= -2 for a free block.  The 8 home buckets are read
+// together (one round trip).
 __device__ __forceinline__ void neighbourhood_slots(const MapDev& m, int bx, int by, int bz, int sl[8]) {
   unsigned long long bkey[8];
   uint32_t bslot[8];
@@ -114,10 +115,15 @@ __global__ __launch_bounds__(256) void raycast_kernel(MapDev m, FrameDev f, cons
         const int o = (((i0[q][0] + dx) >> 3) - base[0]) | ((((i0[q][1] + dy) >> 3) - base[1]) << 1) |
                       ((((i0[q][2] + dz) >> 3) - base[2]) << 2);
         const int s = got[q] ? sl[o & 7] : -1;
-        got[q] = got[q] && s >= 0;
+        got[q] = got[q] && s != -1;
         const uint32_t vi = (uint32_t)(s >= 0 ? s : 0) * 512u +
                             (uint32_t)(((i0[q][0] + dx) & 7) + 8 * ((i0[q][1] + dy) & 7) + 64 * ((i0[q][2] + dz) & 7));
         VoxelStore<STORAGE>::load(m, vi, cs[q][c], cw[q][c]);
+        if (s <= -2) {  // free block (compact free space): (tau, count), unobserved while the count is 0
+          const float fc = (float)(-2 - s);
+          cs[q][c] = fc > 0.0f ? m.tau : 0.0f;
+          cw[q][c] = fc;
+        }
       }
     }
     bool done = false;

@@ -474,7 +474,7 @@ struct CachedSlots {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if ((k & ~cross) != 0) sl[k] = sl[k & cross];
-      ok &= sl[k] >= 0;
+      ok &= sl[k] != -1;  // absent; free blocks (<= -2) read as (tau, count)
     }
     return ok;
   }
