@@ -547,9 +547,6 @@ void allocate(MapBase& m, const Frame& f, const double* T, const uint8_t* mask) 
     }
 }
 
-// Integration (Sections III-A, III-C, III-D): running weighted average of the
-// truncated projective distance, free space carved to tau, masked pixels
-// ignored.  Decisions in FP32; values in Real.
 // Whole-block carving test of the compact free-space reading (FP32, in
 // this order in the kernels too).  Depth cells: per 8x8 pixels, the
 // smallest depth of the cell's measured pixels (D > 0, also beyond the
@@ -613,6 +610,38 @@ bool carve_whole(const Params& P, const Frame& f, const std::vector<float>& cell
   return dmin > zmax + P.truncation + margin;
 }
 
+// The per-voxel rule's decision for voxel l of block b (FP32): 0 no update,
+// 1 band update (d = eta, colour), 2 free-space update (d = tau), 3 no
+// update because the voxel lies more than tau behind its measurement
+// (occluded); for an update, the pixel (u, v) and depth D it came from.
+inline int voxel_kind(const Params& P, const Frame& f, const uint8_t* mask, const float Rf[9], const float tf[3],
+                      const Key& b, int l, int& u, int& v, float& D) {
+  const float s = P.voxel_size, tau = P.truncation, zclip = P.depth_max;
+  int32_t vi[3] = {8*b.x + (l & 7), 8*b.y + ((l >> 3) & 7), 8*b.z + (l >> 6)};
+  // X = R^T (v s - t)
+  float d[3], X[3];
+  for (int a = 0; a < 3; ++a) d[a] = (float)vi[a]*s - tf[a];
+  for (int j = 0; j < 3; ++j) X[j] = (Rf[j]*d[0] + Rf[3+j]*d[1]) + Rf[6+j]*d[2];
+  if (!(X[2] > 0.0f)) return 0;
+  float uf = f.fx*(X[0]/X[2]) + f.cx;
+  float vf = f.fy*(X[1]/X[2]) + f.cy;
+  float ur = std::floor(uf + 0.5f), vr = std::floor(vf + 0.5f);
+  if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) return 0;
+  u = (int)ur;
+  v = (int)vr;
+  D = depth_at(f, u, v);
+  if (!(D > 0.0f)) return 0;  // no measurement
+  if (mask && mask[(size_t)v*f.W + u]) return 0;
+  float eta = D - X[2];
+  if (eta < -tau) return 3;
+  bool band = (eta <= tau);
+  // the band of a measurement beyond depth_max is not integrated; the free
+  // space in front of it is carved like any other (Sec. III-D)
+  if (band && !(D <= P.depth_max)) return 0;
+  if (!band && !(X[2] <= zclip)) return 0;
+  return band ? 1 : 2;
+}
+
 // Integration (Sections III-A, III-C, III-D): running weighted average of the
 // truncated projective distance, free space carved to tau, masked pixels
 // ignored.  Decisions in FP32; values in Real.  counts: band updates, free
@@ -629,27 +658,61 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
   counts[0] = counts[1] = counts[2] = 0;
   std::vector<Key> F = m.last_F;
   std::sort(F.begin(), F.end());
-  // compact free space: the whole-block test of every listed block; a free
-  // block carved whole only counts the frame, any other free block becomes
-  // a block of voxels before the voxel updates
-  std::vector<char> whole(F.size(), 0);
+  // Compact free space: the whole-block test of every listed block.  A free
+  // block carved whole only counts the frame.  Another free block is
+  // evaluated voxel by voxel from its value: if some voxel gets a band
+  // update, or lies occluded behind its measurement (a free value must not
+  // stand for space behind a surface), it becomes a block of voxels
+  // (starting from the free value) and takes the frame's updates below;
+  // otherwise the frame counts for the whole block if it carves any voxel
+  // of it.
+  enum { kPerVoxel = 0, kWhole = 1, kDone = 2, kPending = 3 };
+  std::vector<char> state(F.size(), kPerVoxel);
   int64_t n_whole = 0;
   if (P.free_blocks) {
     int cw = 0;
     const std::vector<float> cells = depth_cells(f, mask, cw);
     for (size_t bi = 0; bi < F.size(); ++bi) {
-      whole[bi] = carve_whole(P, f, cells, cw, Rf, tf, F[bi]) ? 1 : 0;
-      n_whole += whole[bi];
+      const bool whole = carve_whole(P, f, cells, cw, Rf, tf, F[bi]);
+      n_whole += whole;
+      state[bi] = whole ? kWhole : kPerVoxel;
       auto it = m.free_blk.find(F[bi]);
       if (it == m.free_blk.end()) continue;
-      if (whole[bi]) {
+      if (whole) {
         Voxel<Real>& fv = it->second;
         fv.sdf = (Real)tau;
         fv.w = std::min(fv.w + (Real)1, (Real)P.max_weight);
-        whole[bi] = 2;  // done
+        state[bi] = kDone;
       } else {
+        state[bi] = kPending;
+      }
+    }
+    // the pending free blocks' voxel decisions (independent of each other)
+    std::vector<char> any_band(F.size(), 0), any_free(F.size(), 0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (size_t bi = 0; bi < F.size(); ++bi) {
+      if (state[bi] != kPending) continue;
+      for (int l = 0; l < 512; ++l) {
+        int u, v;
+        float D;
+        const int k = voxel_kind(P, f, mask, Rf, tf, F[bi], l, u, v, D);
+        any_band[bi] |= (k == 1 || k == 3);
+        any_free[bi] |= (k == 2);
+      }
+    }
+    for (size_t bi = 0; bi < F.size(); ++bi) {
+      if (state[bi] != kPending) continue;
+      auto it = m.free_blk.find(F[bi]);
+      if (any_band[bi]) {
         m.blocks.emplace(F[bi], std::vector<Voxel<Real>>(512, it->second));
         m.free_blk.erase(it);
+        state[bi] = kPerVoxel;
+      } else {
+        if (any_free[bi]) {
+          it->second.sdf = (Real)tau;
+          it->second.w = std::min(it->second.w + (Real)1, (Real)P.max_weight);
+        }
+        state[bi] = kDone;
       }
     }
   }
@@ -659,9 +722,9 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_band, n_free)
   for (size_t bi = 0; bi < F.size(); ++bi) {
     const Key& b = F[bi];
-    if (whole[bi] == 2) continue;  // free block carved whole
+    if (state[bi] == kDone) continue;  // a free block: counted, no voxels
     auto& blk = m.blocks.at(b);
-    if (whole[bi]) {
+    if (state[bi] == kWhole) {
       // carved whole: every voxel takes the free-space update
       for (int l = 0; l < 512; ++l) {
         Voxel<Real>& vx = blk[l];
@@ -673,30 +736,15 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
       continue;
     }
     for (int l = 0; l < 512; ++l) {
-      int32_t vi[3] = {8*b.x + (l & 7), 8*b.y + ((l >> 3) & 7), 8*b.z + (l >> 6)};
-      // --- FP32 decision path: X = R^T (v s - t)
-      float d[3], X[3];
-      for (int a = 0; a < 3; ++a) d[a] = (float)vi[a]*s - tf[a];
-      for (int j = 0; j < 3; ++j) X[j] = (Rf[j]*d[0] + Rf[3+j]*d[1]) + Rf[6+j]*d[2];
-      if (!(X[2] > 0.0f)) continue;
-      float uf = f.fx*(X[0]/X[2]) + f.cx;
-      float vf = f.fy*(X[1]/X[2]) + f.cy;
-      float ur = std::floor(uf + 0.5f), vr = std::floor(vf + 0.5f);
-      if (!(ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H)) continue;
-      int u = (int)ur, v = (int)vr;
-      float D = depth_at(f, u, v);
-      if (!(D > 0.0f)) continue;  // no measurement
-      if (mask && mask[(size_t)v*f.W + u]) continue;
-      float eta = D - X[2];
-      if (eta < -tau) continue;
-      bool band = (eta <= tau);
-      // the band of a measurement beyond depth_max is not integrated; the free
-      // space in front of it is carved like any other (Sec. III-D)
-      if (band && !(D <= P.depth_max)) continue;
-      if (!band && !(X[2] <= zclip)) continue;
+      int u, v;
+      float D;
+      const int kind = voxel_kind(P, f, mask, Rf, tf, b, l, u, v, D);
+      if (kind == 0 || kind == 3) continue;
+      const bool band = (kind == 1);
       // --- value path in Real
       Real dval;
       if (band) {
+        int32_t vi[3] = {8*b.x + (l & 7), 8*b.y + ((l >> 3) & 7), 8*b.z + (l >> 6)};
         Real dr[3], Xz;
         for (int a = 0; a < 3; ++a) dr[a] = (Real)vi[a]*(Real)s - tr[a];
         Xz = (Rr[2]*dr[0] + Rr[5]*dr[1]) + Rr[8]*dr[2];
