@@ -68,10 +68,11 @@ struct alignas(16) BlockRef {
 };
 constexpr int kMeshScratch = 1024;  // workgroups of the mesh extraction
 constexpr int kCacheLevels = 4;  // pyramid levels with a block cache
-constexpr int kTileRefs = 256;   // largest pair capacity of a tile
+constexpr int kTileRefs = 512;   // largest pair capacity of a tile
 // A 16x16 tile of level l covers 4^l times the area of a level-0 tile, so it
-// touches more blocks: 64 pairs at level 0, 128 at level 1, 256 from level 2.
-__host__ __device__ constexpr int tile_refs(int level) { return level >= 2 ? 256 : 64 << level; }
+// touches more blocks: 64 pairs at level 0, 128 at level 1, 512 from level 2
+// (a level-2 tile of 0.5 cm voxels touches ~110 blocks, up to ~230).
+__host__ __device__ constexpr int tile_refs(int level) { return level >= 2 ? 512 : 64 << level; }
 // First pair of level l's region, in units of tiles (region l holds
 // tc_tiles x tile_refs(l) pairs).
 __host__ __device__ constexpr int tile_refs_before(int level) {
@@ -285,6 +286,16 @@ __device__ __forceinline__ float luminance(float r, float g, float b) {
   const float r255 = 1.0f / 255.0f;
   const float q = x * r255;
   return __builtin_fmaf(__builtin_fmaf(-q, 255.0f, x), r255, q);
+}
+
+// Correctly rounded a / b given y = RN(1/b): one fused Newton correction of
+// the product a y (Markstein); with y the correctly rounded reciprocal the
+// result equals the IEEE quotient for every a and b whose quotient is a
+// normal number (checked exhaustively on the CPU for b = 1..256 and over
+// random pairs for general b).
+__device__ __forceinline__ float quotient_rn(float a, float b, float y) {
+  const float q = a * y;
+  return __builtin_fmaf(__builtin_fmaf(-q, b, a), y, q);
 }
 
 // Float copy of the FP64 pose: R row-major, t.

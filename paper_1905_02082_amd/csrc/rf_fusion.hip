@@ -14,6 +14,8 @@
 // buckets fetched during the current one; only voxels the frame updates are
 // written.  Records are SoA per block, so a workgroup's loads and stores are
 // contiguous 4-KiB (FP32) / 2-KiB (FP16) runs.
+#include <type_traits>
+
 #include "rf_device.h"
 #include "rf_internal.h"
 
@@ -288,8 +290,8 @@ __global__ void reset_frame_list_kernel(Batch b) {
 // indices stay below 2^22).
 constexpr uint32_t kEntryBucket = 0x003FFFFFu;
 constexpr uint32_t kEntryWhole = 0x80000000u;  // carved whole
-constexpr uint32_t kEntryFresh = 0x40000000u;  // pool slot taken now: voxels start from (tau, count)
-constexpr int kEntryCountShift = 22;           // the free block's count (bits 22-29) of a fresh block
+constexpr uint32_t kEntryFresh = 0x40000000u;  // a free block (alone: not carved whole, decided per voxel)
+constexpr int kEntryCountShift = 22;           // the free block's count (bits 22-29)
 constexpr float kCarveMargin = 1.0e-3f;        // metres
 constexpr int kMaxTestCells = 64;
 constexpr int kClassifyGroups = 512;           // workgroups of the whole-block test (all jobs together)
@@ -375,17 +377,9 @@ __global__ __launch_bounds__(256) void classify_kernel(Batch b) {
       const uint32_t c = bk.slot & 0xFFu;
       if (whole) {
         m.buckets[e].slot = kFreeSlot | min(c + 1u, wmax);
-        entry |= kEntryFresh;  // whole + fresh: a free block carved whole, nothing left to do
+        entry |= kEntryFresh;  // whole + free: a free block carved whole, nothing left to do
       } else {
-        uint32_t slot = atomicAdd(&m.st->n_blocks, 1u);
-        if (slot < m.max_blocks) {
-          m.block_keys[slot] = bk.key;
-        } else {
-          slot = kInvalidSlot;
-          atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
-        }
-        m.buckets[e].slot = slot;
-        entry |= kEntryFresh | (c << kEntryCountShift);
+        entry |= kEntryFresh | (c << kEntryCountShift);  // free: decided voxel by voxel
       }
     }
     m.flist[i] = entry;
@@ -423,7 +417,10 @@ __device__ __forceinline__ void take_state(uint32_t bits, uint32_t (&out)[N]) {
   for (int i = 0; i < N; ++i) out[i] = __builtin_amdgcn_readlane(bits, i);
 }
 
-template <int DF, int STORAGE>
+// COMPACT: some job of the batch keeps compact free space (its frame-list
+// entries carry the whole-block test's outcome); without it those paths are
+// compiled out.
+template <int DF, int STORAGE, bool COMPACT>
 __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   constexpr int NV = 2 * kIntegBlocks;  // voxels per thread per step
   const int jb = batch_job(b, blockIdx.x);
@@ -439,6 +436,15 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   load_pose_f(J.pose, R, t);
   uint32_t nb = 0, nf = 0, nw = 0;
   const uint32_t stride = kIntegBlocks * gn;
+  // correctly rounded reciprocals 1 / (W + 1) of the weights 0 .. 255
+  __shared__ float s_rw[256];
+  // compact free space: per pending free block of the step, its voxels'
+  // decisions (bit 0 band or occluded, bit 1 free) and the pool slot it takes
+  __shared__ uint32_t s_pf[kIntegBlocks];
+  __shared__ uint32_t s_pslot[kIntegBlocks];
+  s_rw[threadIdx.x] = 1.0f / (float)(threadIdx.x + 1);
+  if (threadIdx.x < kIntegBlocks) s_pf[threadIdx.x] = 0u;
+  __syncthreads();
   // The list entries and buckets of a step are fetched during the step before
   // it (the list entries while its voxel gathers are in flight, the buckets
   // after them), so a step waits on two round trips instead of four.  Lane i
@@ -451,23 +457,32 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   // frame-list entries of compact free-space maps carry the whole-block
   // test's outcome in their top bits (compact maps keep bucket indices below
   // 2^22); other maps' entries are plain bucket indices
-  const uint32_t bucket_bits = m.free_blocks ? kEntryBucket : 0xFFFFFFFFu;
+  const uint32_t bucket_bits = (COMPACT && m.free_blocks) ? kEntryBucket : 0xFFFFFFFFu;
   Bucket cur[kIntegBlocks];
-  uint32_t cur_st[kIntegBlocks];
+  uint32_t cur_e[kIntegBlocks];
   if (g0 < nF) {
     const uint32_t fi = g0 + my_i * gn;
     const uint32_t e = m.flist[fi < nF ? fi : g0];
     const Bucket bq = m.buckets[e & bucket_bits];
     take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
-    take_state<kIntegBlocks>(e & ~bucket_bits, cur_st);
+    take_state<kIntegBlocks>(e, cur_e);
   }
   for (uint32_t f0 = g0; f0 < nF; f0 += stride) {
     Bucket bu[kIntegBlocks];
-    uint32_t st[kIntegBlocks];  // uniform: the block's whole-block test outcome
+    uint32_t st[kIntegBlocks];  // uniform: the whole-block test's outcome
+    uint32_t eb[kIntegBlocks];  // uniform: bucket index
+    bool live[kIntegBlocks], whole[kIntegBlocks], pend[kIntegBlocks];
 #pragma unroll
     for (int i = 0; i < kIntegBlocks; ++i) {
       bu[i] = cur[i];
-      st[i] = cur_st[i];
+      st[i] = COMPACT ? (cur_e[i] & ~bucket_bits) : 0u;
+      eb[i] = cur_e[i] & bucket_bits;
+      whole[i] = (st[i] & kEntryWhole) != 0u;
+      // a free block not carved whole: evaluated voxel by voxel from its
+      // free value, it takes a pool slot below if a voxel gets a band update
+      pend[i] = (st[i] & (kEntryWhole | kEntryFresh)) == kEntryFresh;
+      // a free block carved whole has nothing left to update
+      live[i] = f0 + i * gn < nF && (bu[i].slot < m.max_blocks || pend[i]) && !(whole[i] && (st[i] & kEntryFresh));
     }
     // the next step's list entries (past the list's end: this step's first
     // entry again, so the loads stay unconditional and in bounds)
@@ -482,11 +497,9 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
     for (int v = 0; v < NV; ++v) {
       const int i = v >> 1;
       const int l = threadIdx.x + 256 * (v & 1);
-      const bool whole = (st[i] & kEntryWhole) != 0u, fresh = (st[i] & kEntryFresh) != 0u;
-      // a free block carved whole has nothing left to update
-      const bool ok = f0 + i * gn < nF && bu[i].slot < m.max_blocks && !(whole && fresh);
-      vidx[v] = ok ? bu[i].slot * 512u + (uint32_t)l : 0u;
-      if (whole) {  // a block of voxels carved whole: no projection, no pixel
+      const bool ok = live[i];
+      vidx[v] = (ok && !pend[i]) ? bu[i].slot * 512u + (uint32_t)l : 0u;
+      if (whole[i]) {  // a block of voxels carved whole: no projection, no pixel
         pix[v] = 0;
         X2[v] = 0.0f;
         vis[v] = ok;
@@ -502,8 +515,11 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       const float x1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
       const float x2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
       bool in = ok && x2 > 0.0f;
-      const float uf = f.fx * (x0 / x2) + f.cx;
-      const float vf = f.fy * (x1 / x2) + f.cy;
+      // x0 / x2 and x1 / x2 from one correctly rounded reciprocal (exact
+      // quotients; x2 > 0 and the pixel test reject the rest)
+      const float iz = 1.0f / x2;
+      const float uf = f.fx * quotient_rn(x0, x2, iz) + f.cx;
+      const float vf = f.fy * quotient_rn(x1, x2, iz) + f.cy;
       const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
       in = in && ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H;
       pix[v] = in ? (int)vr * f.W + (int)ur : 0;
@@ -516,63 +532,122 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
     for (int v = 0; v < NV; ++v) {
       D[v] = 0.0f;
       mk[v] = 0u;
-      if (!(st[v >> 1] & kEntryWhole)) {
+      if (!whole[v >> 1]) {
         D[v] = load_depth<DF>(f, pix[v]);
         mk[v] = mask_src[pix[v]];
       }
-      if (!(st[v >> 1] & kEntryFresh)) VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
+      if (!pend[v >> 1]) VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(D[v]), "+v"(mk[v]), "+v"(sdf[v]), "+v"(W[v]));
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      if (!(st[v >> 1] & kEntryFresh)) continue;
-      // a free block that takes its pool slot now: every voxel starts from
-      // the free block's value (tau and its count; unobserved while 0)
+      if (!pend[v >> 1]) continue;
+      // a pending free block: every voxel starts from the free value (tau
+      // and its count; unobserved while 0)
       const float c = (float)((st[v >> 1] >> kEntryCountShift) & 0xFFu);
       sdf[v] = c > 0.0f ? m.tau : 0.0f;
       W[v] = c;
     }
+    // RN(1 / (W + 1)) of every voxel: from the table for the integral
+    // weights the integration writes (0 .. 255), by division otherwise
+    float rw[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int wi = (int)W[v];
+      const bool tab = wi >= 0 && wi < 256 && (float)wi == W[v];
+      rw[v] = s_rw[tab ? wi : 0];
+      if (!tab) rw[v] = 1.0f / (W[v] + 1.0f);
+    }
     const Bucket bq = m.buckets[hn & bucket_bits];  // the next step's buckets
-    // sdf and weight of every updated voxel; the band voxels then update
-    // their colour, with all colour loads of the step (the voxel's and the
-    // frame's) issued together
-    bool band[NV];
+    // the per-voxel rule's decision and the new sdf of every voxel (occl:
+    // no update because the voxel lies more than tau behind its measurement)
+    bool band[NV], upd[NV], occl[NV];
+    float nsdf[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       band[v] = false;
-      if (st[v >> 1] & kEntryWhole) {  // carved whole: the free-space update
-        if (!vis[v]) continue;
-        VoxelStore<STORAGE>::store(m, vidx[v], (W[v] * sdf[v] + m.tau) / (W[v] + 1.0f),
-                                   fminf(W[v] + 1.0f, m.max_weight));
-        nf += 1;
-        continue;
-      }
-      // a fresh block writes every voxel (its pool slot held nothing); the
-      // others write the voxels the frame updates
-      const int i = v >> 1;
-      const bool fresh = (st[i] & kEntryFresh) != 0u && f0 + i * gn < nF && bu[i].slot < m.max_blocks;
-      bool upd = false;
-      float dval = 0.0f;
-      if (vis[v] && D[v] > 0.0f && !(mask && mk[v])) {
+      upd[v] = false;
+      occl[v] = false;
+      float dval = m.tau;
+      if (whole[v >> 1]) {
+        upd[v] = vis[v];  // carved whole: the free-space update
+      } else if (vis[v] && D[v] > 0.0f && !(mask && mk[v])) {
         const float eta = D[v] - X2[v];
+        occl[v] = eta < -m.tau;
         if (eta >= -m.tau) {
           const bool bnd = eta <= m.tau;
           // the band of a measurement beyond depth_max is not integrated; the
           // free space in front of it is carved like any other (Sec. III-D)
           if (bnd ? (D[v] <= m.dmax) : (X2[v] <= m.dmax)) {
-            upd = true;
+            upd[v] = true;
             band[v] = bnd;
             dval = bnd ? eta : m.tau;
           }
         }
       }
-      if (upd) {
-        VoxelStore<STORAGE>::store(m, vidx[v], (W[v] * sdf[v] + dval) / (W[v] + 1.0f),
-                                   fminf(W[v] + 1.0f, m.max_weight));
+      nsdf[v] = quotient_rn(W[v] * sdf[v] + dval, W[v] + 1.0f, rw[v]);
+    }
+    // pending free blocks: a band update or an occluded voxel anywhere in the
+    // block gives it a pool slot (all its voxels are then written; a free
+    // value must not stand for space behind a surface); otherwise the frame
+    // counts for the whole block if it carves any voxel of it
+    bool fresh[kIntegBlocks];
+#pragma unroll
+    for (int i = 0; i < kIntegBlocks; ++i) fresh[i] = false;
+    if (COMPACT && (pend[0] || pend[1])) {  // uniform
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (pend[v >> 1] && live[v >> 1] && (upd[v] || occl[v]))
+          atomicOr(&s_pf[v >> 1], (band[v] || occl[v]) ? 1u : 2u);
+      __syncthreads();
+      if (threadIdx.x < kIntegBlocks) {
+        const int i = threadIdx.x;
+        uint32_t slot = kInvalidSlot;
+        if (pend[i] && live[i]) {
+          const uint32_t fl = s_pf[i];
+          const uint32_t c = (st[i] >> kEntryCountShift) & 0xFFu;
+          if (fl & 1u) {
+            slot = atomicAdd(&m.st->n_blocks, 1u);
+            if (slot < m.max_blocks) {
+              m.block_keys[slot] = bu[i].key;
+            } else {
+              slot = kInvalidSlot;
+              atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
+            }
+            m.buckets[eb[i]].slot = slot;
+          } else if (fl & 2u) {
+            m.buckets[eb[i]].slot = kFreeSlot | min(c + 1u, (uint32_t)m.max_weight);
+          }
+        }
+        s_pslot[i] = slot;
+        s_pf[i] = 0u;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kIntegBlocks; ++i) {
+        if (!pend[i]) continue;
+        const uint32_t slot = s_pslot[i];
+        fresh[i] = slot < m.max_blocks;
+        if (fresh[i]) bu[i].slot = slot;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (fresh[v >> 1]) vidx[v] = bu[v >> 1].slot * 512u + (uint32_t)(threadIdx.x + 256 * (v & 1));
+    }
+    // stores: updated voxels; every voxel of a block that takes its pool slot now
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int i = v >> 1;
+      if (pend[i] && !fresh[i]) {
+        band[v] = false;  // stays a free block: nothing stored
+        continue;
+      }
+      if (upd[v]) {
+        VoxelStore<STORAGE>::store(m, vidx[v], nsdf[v], fminf(W[v] + 1.0f, m.max_weight));
         nb += band[v];
         nf += !band[v];
-      } else if (fresh) {
+      } else if (fresh[i]) {
         VoxelStore<STORAGE>::store(m, vidx[v], sdf[v], W[v]);
       }
     }
@@ -582,7 +657,7 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       cold[v] = 0u;
       cpx[v][0] = cpx[v][1] = cpx[v][2] = 0u;
       if (!band[v]) continue;
-      if (!(st[v >> 1] & kEntryFresh)) cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
+      if (!fresh[v >> 1]) cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
       const uint8_t* px = f.rgb + 3 * pix[v];
       cpx[v][0] = px[0];
       cpx[v][1] = px[1];
@@ -591,9 +666,9 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]), "+v"(cpx[v][2]));
     take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
-    take_state<kIntegBlocks>(hn & ~bucket_bits, cur_st);
+    take_state<kIntegBlocks>(hn, cur_e);
 #pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) nw += ((st[i] & kEntryWhole) && f0 + i * gn < nF) ? 1u : 0u;
+    for (int i = 0; i < kIntegBlocks; ++i) nw += (whole[i] && f0 + i * gn < nF) ? 1u : 0u;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if (!band[v]) continue;
@@ -601,7 +676,8 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       float ch[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        ch[q] = fminf(255.0f, fmaxf(0.0f, rintf((Wv * (float)((cold[v] >> (8 * q)) & 0xFFu) + (float)cpx[v][q]) / Wn)));
+        ch[q] = fminf(255.0f, fmaxf(0.0f, rintf(quotient_rn(Wv * (float)((cold[v] >> (8 * q)) & 0xFFu) + (float)cpx[v][q],
+                                                            Wn, rw[v]))));
       m.rgb[vidx[v]] = make_uchar4((unsigned char)ch[0], (unsigned char)ch[1], (unsigned char)ch[2], 0);
     }
   }
@@ -704,13 +780,18 @@ void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
   const int per = kIntegGroups / b.n;
   for (int j = 0; j <= b.n; ++j) b.base[j] = j * per;
   const int grid = b.n * per;
-  if (depth_format == RF_DEPTH_U16) {
-    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP32><<<grid, 256, 0, s>>>(b);
-    else integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(b);
-  } else {
-    if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP32><<<grid, 256, 0, s>>>(b);
-    else integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8><<<grid, 256, 0, s>>>(b);
-  }
+  auto run = [&](auto compact) {
+    constexpr bool C = decltype(compact)::value;
+    if (depth_format == RF_DEPTH_U16) {
+      if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP32, C><<<grid, 256, 0, s>>>(b);
+      else integrate_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8, C><<<grid, 256, 0, s>>>(b);
+    } else {
+      if (storage == RF_STORAGE_FP32) integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP32, C><<<grid, 256, 0, s>>>(b);
+      else integrate_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8, C><<<grid, 256, 0, s>>>(b);
+    }
+  };
+  if (compact) run(std::true_type{});
+  else run(std::false_type{});
   integ_fold_kernel<<<b.n, 256, 0, s>>>(b);
 }
 

@@ -22,6 +22,8 @@
 // buffers (read j-1, write j, clear j+1) and the pose through two, so no
 // launch reads what the same launch writes.  A one-workgroup finalize launch
 // solves the last iteration and writes the caller's pose.
+#include <type_traits>
+
 #include "rf_device.h"
 #include "rf_internal.h"
 
@@ -362,17 +364,18 @@ __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& 
 // next launch at this level and tile.  A slot still being written reads as
 // kNoSlot, which a lookup treats as a miss, so concurrent inserts never
 // yield a wrong slot.
-constexpr int kHashSlots = kTileRefs;
 constexpr int kNoSlot = (int)0x80000000;
 constexpr int kMaxProbe = 8;   // a key is placed within 8 slots of its home or not cached
 constexpr int kWin = 8;        // direct-mapped window of kWin^3 blocks around the tile's blocks
 constexpr int kWinCells = kWin * kWin * kWin;
 constexpr int kFarOrigin = 0x40000000;  // window origin that no block coordinate reaches
 
+// SLOTS: LDS hash capacity (the tile's pair capacity at the launch's level).
+template <int SLOTS>
 struct TileCache {
-  unsigned long long* key;  // kHashSlots, kEmptyKey when free
-  int* slot;                // kHashSlots, kNoSlot until written
-  uint8_t* used;            // kHashSlots, 1 when looked up in this launch
+  unsigned long long* key;  // SLOTS, kEmptyKey when free
+  int* slot;                // SLOTS, kNoSlot until written
+  uint8_t* used;            // SLOTS, 1 when looked up in this launch
   int* grid;                // kWin^3 window of block slots (kNoSlot: unknown)
   uint8_t* gused;           // kWin^3, 1 when looked up in this launch
   int ax, ay, az;           // window origin (block coordinates)
@@ -384,7 +387,7 @@ struct TileCache {
   }
 
   __device__ __forceinline__ void insert(int x, int y, int z, unsigned long long k, int sl, bool mark) const {
-    uint32_t h = hash3(x, y, z) & (kHashSlots - 1);
+    uint32_t h = hash3(x, y, z) & (SLOTS - 1);
 #pragma unroll 1
     for (int i = 0; i < kMaxProbe; ++i) {
       const unsigned long long old = atomicCAS(&key[h], kEmptyKey, k);
@@ -397,12 +400,12 @@ struct TileCache {
         if (mark) used[h] = 1;
         return;
       }
-      h = (h + 1) & (kHashSlots - 1);
+      h = (h + 1) & (SLOTS - 1);
     }
   }
 
   __device__ __forceinline__ int find(int x, int y, int z, unsigned long long k) const {
-    uint32_t h = hash3(x, y, z) & (kHashSlots - 1);
+    uint32_t h = hash3(x, y, z) & (SLOTS - 1);
 #pragma unroll 1
     for (int i = 0; i < kMaxProbe; ++i) {
       const unsigned long long kk = key[h];
@@ -412,7 +415,7 @@ struct TileCache {
         return sl;
       }
       if (kk == kEmptyKey) break;
-      h = (h + 1) & (kHashSlots - 1);
+      h = (h + 1) & (SLOTS - 1);
     }
     return kNoSlot;
   }
@@ -421,8 +424,9 @@ struct TileCache {
 // Slot resolution of sample_map through the tile cache: cached blocks cost
 // an LDS probe; the others take the hash table (first probes of all missing
 // corner blocks issued together) and are added to the cache.
+template <int SLOTS>
 struct CachedSlots {
-  TileCache c;
+  TileCache<SLOTS> c;
   __device__ __forceinline__ bool operator()(const MapDev& m, int bx0, int by0, int bz0, int cross, int sl[8]) const {
     // window cells of all eight corner blocks read together (one LDS round trip)
 #pragma unroll
@@ -480,7 +484,10 @@ struct CachedSlots {
   }
 };
 
-template <int DF, int STORAGE, bool LM>
+// SLOTS: pairs the tile cache holds in LDS (256 at levels 0-1, 512 at the
+// coarser levels, whose few tiles each touch more blocks; more LDS and
+// registers there cost nothing, since those launches have few workgroups).
+template <int DF, int STORAGE, bool LM, int SLOTS>
 __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a) {
   __shared__ float s_t[kTerms][kTrackBlock + 1];
   __shared__ double s_g[kNE][kGroups + 1];
@@ -489,9 +496,9 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   __shared__ double s_st[kLmWords];
   __shared__ double s_T[16];
   __shared__ int s_state;
-  __shared__ unsigned long long s_hk[kHashSlots];
-  __shared__ int s_hs[kHashSlots];
-  __shared__ uint8_t s_used[kHashSlots];
+  __shared__ unsigned long long s_hk[SLOTS];
+  __shared__ int s_hs[SLOTS];
+  __shared__ uint8_t s_used[SLOTS];
   __shared__ int s_grid[kWinCells];
   __shared__ uint8_t s_gused[kWinCells];
   __shared__ int s_org[3];
@@ -544,13 +551,13 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   const int nrefs = tile_refs(a.level);
   if (wave == 1) {
     const BlockRef none{kEmptyKey, -1, 0u};
-    constexpr int kLoads = kTileRefs / 64;
+    constexpr int kLoads = SLOTS / 64;
     const int cnt = cached ? (int)min(*tcount, (uint32_t)nrefs) : 0;
     BlockRef e[kLoads];
 #pragma unroll
     for (int q = 0; q < kLoads; ++q) e[q] = (cached && lane + 64 * q < nrefs) ? tab[lane + 64 * q] : none;
 #pragma unroll
-    for (int q = 0; q < kHashSlots / 64; ++q) {
+    for (int q = 0; q < SLOTS / 64; ++q) {
       s_hk[lane + 64 * q] = kEmptyKey;
       s_hs[lane + 64 * q] = kNoSlot;
       s_used[lane + 64 * q] = 0;
@@ -595,7 +602,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const TileCache wc{s_hk, s_hs, s_used, s_grid, s_gused, org[0], org[1], org[2]};
+    const TileCache<SLOTS> wc{s_hk, s_hs, s_used, s_grid, s_gused, org[0], org[1], org[2]};
 #pragma unroll
     for (int q = 0; q < kLoads; ++q) {
       if (!v[q]) continue;
@@ -626,7 +633,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   }
   __syncthreads();
   if (stopped || s_state != 0) return;  // stopped or degenerate: pose kept, the pass stops
-  const TileCache cache{s_hk, s_hs, s_used, s_grid, s_gused, s_org[0], s_org[1], s_org[2]};
+  const TileCache<SLOTS> cache{s_hk, s_hs, s_used, s_grid, s_gused, s_org[0], s_org[1], s_org[2]};
 
   float term[kTerms];
 #pragma unroll
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     float y[3];
     xform(R, t, x, y);
     float S, gS[3], Iv, gI[3];
-    if (sample_map<STORAGE, true, true>(m, y, S, gS, Iv, gI, CachedSlots{cache}) && fabsf(S) < m.tau) {
+    if (sample_map<STORAGE, true, true>(m, y, S, gS, Iv, gI, CachedSlots<SLOTS>{cache}) && fabsf(S) < m.tau) {
       term[0] = gS[0];
       term[1] = gS[1];
       term[2] = gS[2];
@@ -675,7 +682,7 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
         if (pos < (uint32_t)nrefs) tab[pos] = BlockRef{kk, ss, epoch};
       }
     }
-    for (int h = threadIdx.x; h < kHashSlots; h += kTrackBlock) {
+    for (int h = threadIdx.x; h < SLOTS; h += kTrackBlock) {
       const unsigned long long kk = s_hk[h];
       const int ss = s_hs[h];
       if (kk != kEmptyKey && ss != kNoSlot && s_used[h]) {
@@ -788,22 +795,27 @@ static void track_dispatch(Batch& b, int df, int st, const TrackArgs& a, hipStre
   }
   b.base[b.n] = total;
   const dim3 g(total), blk(kTrackBlock);
+  auto run = [&](auto lm, auto slots) {
+    constexpr bool L = decltype(lm)::value;
+    constexpr int S = decltype(slots)::value;
+    if (df == RF_DEPTH_U16) {
+      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32, L, S><<<g, blk, 0, s>>>(b, a);
+      else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8, L, S><<<g, blk, 0, s>>>(b, a);
+    } else {
+      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32, L, S><<<g, blk, 0, s>>>(b, a);
+      else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8, L, S><<<g, blk, 0, s>>>(b, a);
+    }
+  };
+  using Small = std::integral_constant<int, tile_refs(1) * 2>;
+  using Large = std::integral_constant<int, kTileRefs>;
+  static_assert(tile_refs(0) <= Small::value && tile_refs(1) <= Small::value, "level 0-1 pairs fit the small cache");
+  const bool big = a.level >= 2;
   if (a.adaptive) {
-    if (df == RF_DEPTH_U16) {
-      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32, true><<<g, blk, 0, s>>>(b, a);
-      else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8, true><<<g, blk, 0, s>>>(b, a);
-    } else {
-      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32, true><<<g, blk, 0, s>>>(b, a);
-      else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8, true><<<g, blk, 0, s>>>(b, a);
-    }
+    if (big) run(std::true_type{}, Large{});
+    else run(std::true_type{}, Small{});
   } else {
-    if (df == RF_DEPTH_U16) {
-      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_U16, RF_STORAGE_FP32, false><<<g, blk, 0, s>>>(b, a);
-      else track_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8, false><<<g, blk, 0, s>>>(b, a);
-    } else {
-      if (st == RF_STORAGE_FP32) track_kernel<RF_DEPTH_F32, RF_STORAGE_FP32, false><<<g, blk, 0, s>>>(b, a);
-      else track_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8, false><<<g, blk, 0, s>>>(b, a);
-    }
+    if (big) run(std::false_type{}, Large{});
+    else run(std::false_type{}, Small{});
   }
 }
 
