@@ -431,7 +431,8 @@ def serving_bench(args):
     mp = rf.MaskParams(0.5, 0.007)
     budget = int(args.hbm_budget_gib * 2**30)
     r = serving.serve(specs, tp, mp, budget, max_batch=args.max_batch, depth=2, device=dev,
-                      progress=lambda st, c, t: log("serving: step %d, %d/%d frames" % (st, c, t)))
+                      progress=lambda st, c, t: log("serving: step %d, %d/%d frames" % (st, c, t)),
+                      batch_window_ms=args.batch_window_ms)
     summ = r.summary()
     out = {"metric": "aggregate frames/s of %d concurrent mixed-resolution sessions; p50/p99 frame latency"
                      % n_sess,
@@ -441,9 +442,10 @@ def serving_bench(args):
            "data": "synthetic",
            "config": {"workload": "serving: %d sessions, 30%% 320x240 / 50%% 640x480 / 20%% 1280x720, "
                                   "%s arrivals, lengths U[300,2000] x %.3g frames, %s storage, HBM budget %.1f GiB, "
-                                  "max batch %d" % (n_sess, "unpaced" if args.unpaced else "Poisson 30 fps",
-                                                    args.serve_scale, args.storage or "fp16",
-                                                    args.hbm_budget_gib, args.max_batch)},
+                                  "max batch %d, batch window %.3g ms"
+                                  % (n_sess, "unpaced" if args.unpaced else "Poisson 30 fps",
+                                     args.serve_scale, args.storage or "fp16",
+                                     args.hbm_budget_gib, args.max_batch, args.batch_window_ms)},
            "latency_ms": summ["latency_ms"], "serving": summ}
     print(json.dumps(out), flush=True)
 
@@ -470,6 +472,8 @@ def main():
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="serving: admission budget")
     ap.add_argument("--max-batch", type=int, default=64, help="serving: sessions per step")
     ap.add_argument("--unpaced", action="store_true", help="serving: all frames available at once")
+    ap.add_argument("--batch-window-ms", type=float, default=0.0,
+                    help="serving: while a step runs, the next waits up to this long for more ready frames")
     ap.add_argument("--batch", type=int, default=1,
                     help="sessions processed together per step (1..8; the same scene at staggered frames)")
     ap.add_argument("--no-mesh", action="store_true", help="skip the mesh extraction measurement after the timed region")
@@ -594,6 +598,12 @@ def main():
                                "sample": samplen, "cpu_model": model, "nproc": ncpu,
                                "single_thread": {"value": round(v1, 5), "cores": 1, "sample": sample1}}
     print(json.dumps(out), flush=True)
+    # release every map (and its arena) and drain the stream before the
+    # interpreter shuts down, so no destructor runs against a torn-down runtime
+    frames = None
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -107,8 +107,14 @@ class _Live:
 
 
 def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget: int, max_batch=64, depth=2,
-          dynamic=True, device="cuda", pinned_frames=None, progress=None, on_finish=None) -> ServeResult:
+          dynamic=True, device="cuda", pinned_frames=None, progress=None, on_finish=None,
+          batch_window_ms=0.0) -> ServeResult:
     """Runs all sessions to completion; returns latency and throughput.
+
+    batch_window_ms: while a step is already running on the GPU, a further
+    step waits until max_batch frames are ready or its oldest frame has
+    waited this long (0: it is issued as soon as one frame is ready).  An
+    idle GPU always takes the ready frames at once.
 
     on_finish(spec, session), if given, is called once per session after its
     last frame has completed and before its map is released (the session's
@@ -195,7 +201,9 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
         ready = [lv for lv in live if lv.next < len(lv.spec.arrivals) and lv.arrival(lv.next) <= t]
         ready.sort(key=lambda lv: lv.arrival(lv.next))
         ready = ready[:max_batch]
-        if ready and len(inflight) < depth:
+        hold = (batch_window_ms > 0.0 and inflight and len(ready) < max_batch and ready and
+                (t - ready[0].arrival(ready[0].next)) * 1000.0 < batch_window_ms)
+        if ready and len(inflight) < depth and not hold:
             frames, members, keep = [], [], []
             for lv in ready:
                 seq = lv.spec.seq
@@ -216,6 +224,8 @@ def serve(specs: List[SessionSpec], tp: TrackParams, mp: MaskParams, hbm_budget:
         else:
             if inflight:
                 retire(block=len(inflight) >= depth or not ready)
+                if hold:
+                    time.sleep(0.0002)
             elif not ready:
                 # idle until the next arrival (or admission retry)
                 nxt = [lv.arrival(lv.next) for lv in live if lv.next < len(lv.spec.arrivals)]
