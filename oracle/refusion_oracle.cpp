@@ -611,9 +611,8 @@ bool carve_whole(const Params& P, const Frame& f, const std::vector<float>& cell
 }
 
 // The per-voxel rule's decision for voxel l of block b (FP32): 0 no update,
-// 1 band update (d = eta, colour), 2 free-space update (d = tau), 3 no
-// update because the voxel lies more than tau behind its measurement
-// (occluded); for an update, the pixel (u, v) and depth D it came from.
+// 1 band update (d = eta, colour), 2 free-space update (d = tau); for an
+// update, the pixel (u, v) and depth D it came from.
 inline int voxel_kind(const Params& P, const Frame& f, const uint8_t* mask, const float Rf[9], const float tf[3],
                       const Key& b, int l, int& u, int& v, float& D) {
   const float s = P.voxel_size, tau = P.truncation, zclip = P.depth_max;
@@ -633,7 +632,7 @@ inline int voxel_kind(const Params& P, const Frame& f, const uint8_t* mask, cons
   if (!(D > 0.0f)) return 0;  // no measurement
   if (mask && mask[(size_t)v*f.W + u]) return 0;
   float eta = D - X[2];
-  if (eta < -tau) return 3;
+  if (eta < -tau) return 0;  // behind the surface
   bool band = (eta <= tau);
   // the band of a measurement beyond depth_max is not integrated; the free
   // space in front of it is carved like any other (Sec. III-D)
@@ -660,12 +659,11 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
   std::sort(F.begin(), F.end());
   // Compact free space: the whole-block test of every listed block.  A free
   // block carved whole only counts the frame.  Another free block is
-  // evaluated voxel by voxel from its value: if some voxel gets a band
-  // update, or lies occluded behind its measurement (a free value must not
-  // stand for space behind a surface), it becomes a block of voxels
-  // (starting from the free value) and takes the frame's updates below;
-  // otherwise the frame counts for the whole block if it carves any voxel
-  // of it.
+  // evaluated voxel by voxel: if some voxel gets a band update it becomes a
+  // block of voxels (starting from the free value) and takes the frame's
+  // updates below; if every voxel is carved the frame counts for it; else
+  // (some carved, some not updated) it is left as it is, so a free block's
+  // value always stands for space observed free in all of its voxels.
   enum { kPerVoxel = 0, kWhole = 1, kDone = 2, kPending = 3 };
   std::vector<char> state(F.size(), kPerVoxel);
   int64_t n_whole = 0;
@@ -688,17 +686,20 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
       }
     }
     // the pending free blocks' voxel decisions (independent of each other)
-    std::vector<char> any_band(F.size(), 0), any_free(F.size(), 0);
+    std::vector<char> any_band(F.size(), 0), all_free(F.size(), 0);
 #pragma omp parallel for schedule(dynamic, 16)
     for (size_t bi = 0; bi < F.size(); ++bi) {
       if (state[bi] != kPending) continue;
+      bool band = false, all = true;
       for (int l = 0; l < 512; ++l) {
         int u, v;
         float D;
         const int k = voxel_kind(P, f, mask, Rf, tf, F[bi], l, u, v, D);
-        any_band[bi] |= (k == 1 || k == 3);
-        any_free[bi] |= (k == 2);
+        band |= (k == 1);
+        all &= (k == 2);
       }
+      any_band[bi] = band;
+      all_free[bi] = all;
     }
     for (size_t bi = 0; bi < F.size(); ++bi) {
       if (state[bi] != kPending) continue;
@@ -708,7 +709,7 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
         m.free_blk.erase(it);
         state[bi] = kPerVoxel;
       } else {
-        if (any_free[bi]) {
+        if (all_free[bi]) {
           it->second.sdf = (Real)tau;
           it->second.w = std::min(it->second.w + (Real)1, (Real)P.max_weight);
         }
@@ -739,7 +740,7 @@ void integrate(Map<Real>& m, const Frame& f, const double* T, const uint8_t* mas
       int u, v;
       float D;
       const int kind = voxel_kind(P, f, mask, Rf, tf, b, l, u, v, D);
-      if (kind == 0 || kind == 3) continue;
+      if (kind == 0) continue;
       const bool band = (kind == 1);
       // --- value path in Real
       Real dval;

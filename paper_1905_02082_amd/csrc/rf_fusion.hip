@@ -439,7 +439,8 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   // correctly rounded reciprocals 1 / (W + 1) of the weights 0 .. 255
   __shared__ float s_rw[256];
   // compact free space: per pending free block of the step, its voxels'
-  // decisions (bit 0 band or occluded, bit 1 free) and the pool slot it takes
+  // decisions (bit 0 some band update, bit 1 some voxel not carved) and the
+  // pool slot it takes
   __shared__ uint32_t s_pf[kIntegBlocks];
   __shared__ uint32_t s_pslot[kIntegBlocks];
   s_rw[threadIdx.x] = 1.0f / (float)(threadIdx.x + 1);
@@ -560,21 +561,18 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       if (!tab) rw[v] = 1.0f / (W[v] + 1.0f);
     }
     const Bucket bq = m.buckets[hn & bucket_bits];  // the next step's buckets
-    // the per-voxel rule's decision and the new sdf of every voxel (occl:
-    // no update because the voxel lies more than tau behind its measurement)
-    bool band[NV], upd[NV], occl[NV];
+    // the per-voxel rule's decision and the new sdf of every voxel
+    bool band[NV], upd[NV];
     float nsdf[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       band[v] = false;
       upd[v] = false;
-      occl[v] = false;
       float dval = m.tau;
       if (whole[v >> 1]) {
         upd[v] = vis[v];  // carved whole: the free-space update
       } else if (vis[v] && D[v] > 0.0f && !(mask && mk[v])) {
         const float eta = D[v] - X2[v];
-        occl[v] = eta < -m.tau;
         if (eta >= -m.tau) {
           const bool bnd = eta <= m.tau;
           // the band of a measurement beyond depth_max is not integrated; the
@@ -588,18 +586,17 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       }
       nsdf[v] = quotient_rn(W[v] * sdf[v] + dval, W[v] + 1.0f, rw[v]);
     }
-    // pending free blocks: a band update or an occluded voxel anywhere in the
-    // block gives it a pool slot (all its voxels are then written; a free
-    // value must not stand for space behind a surface); otherwise the frame
-    // counts for the whole block if it carves any voxel of it
+    // pending free blocks: a band update anywhere in the block gives it a pool
+    // slot (all its voxels are then written); otherwise the frame counts for
+    // the block if it carves every voxel of it, and leaves it as it is if not
+    // (its value stands for space observed free in all of its voxels)
     bool fresh[kIntegBlocks];
 #pragma unroll
     for (int i = 0; i < kIntegBlocks; ++i) fresh[i] = false;
     if (COMPACT && (pend[0] || pend[1])) {  // uniform
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        if (pend[v >> 1] && live[v >> 1] && (upd[v] || occl[v]))
-          atomicOr(&s_pf[v >> 1], (band[v] || occl[v]) ? 1u : 2u);
+        if (pend[v >> 1] && live[v >> 1] && (band[v] || !upd[v])) atomicOr(&s_pf[v >> 1], band[v] ? 1u : 2u);
       __syncthreads();
       if (threadIdx.x < kIntegBlocks) {
         const int i = threadIdx.x;
@@ -616,7 +613,7 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
               atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
             }
             m.buckets[eb[i]].slot = slot;
-          } else if (fl & 2u) {
+          } else if (!(fl & 2u)) {
             m.buckets[eb[i]].slot = kFreeSlot | min(c + 1u, (uint32_t)m.max_weight);
           }
         }

@@ -7,10 +7,12 @@ Reading: a block whose 8 corner voxels lie in front of the clipping plane
 and project, with a one-pixel border, into a part of the image where every
 8x8 cell has a measured, unmasked depth more than tau (+1 mm) beyond the
 block's farthest corner is carved whole (every voxel takes the free-space
-update).  A block that has only ever been carved whole is a free block: no
-voxels, one value (sdf tau, weight = frames that carved it) that all its
-voxels read as; it becomes a block of voxels starting from that value the
-first time a frame does not carve it whole."""
+update).  A new block is a free block: no voxels, one value (sdf tau, weight
+= frames that carved all of its voxels) that all its voxels read as.  A frame
+that carves it whole, or carves every one of its voxels by the per-voxel
+rule, adds one to the weight; a band update of any voxel turns it into a
+block of voxels starting from that value; any other frame leaves it as it
+is, so the value only ever stands for space observed free in every voxel."""
 import numpy as np
 import pytest
 
@@ -49,14 +51,12 @@ def fuse(m, frames, poses, masks=None):
 
 @pytest.mark.parametrize("bits", [64, 32])
 def test_first_frame_against_per_voxel_carving(bits):
-    """With every pixel measured, after the first frame a block holds voxels
-    when per-voxel carving gave one of its voxels a band update (or left one
-    occluded behind its measurement), and then holds exactly the per-voxel
-    map's voxels; every other listed block
-    is a free block whose per-voxel counterpart holds only carved voxels
-    (tau, 1) and unobserved ones, of weight 1 if any voxel was carved and 0
-    otherwise (the block test is sound: a block carved whole has no band
-    voxel)."""
+    """With every pixel measured, after the first frame the blocks holding
+    voxels are exactly those where per-voxel carving gave a voxel a band
+    update, and they hold exactly the per-voxel map's voxels; every other
+    listed block is a free block of weight 1 when per-voxel carving carved
+    all 512 of its voxels (tau, 1) and of weight 0 otherwise (so the block
+    test is sound: a block carved whole has every voxel carved)."""
     room = synth.parity_room(n_frames=3)
     fr = O.Frame(room.depth[0], room.rgb[0], *room.intrinsics)
     assert (room.depth[0] > 0).all()
@@ -70,40 +70,48 @@ def test_first_frame_against_per_voxel_carving(bits):
     assert b.num_blocks == a.num_blocks == len(comp) + len(fk)
     tau = float(np.float32(room.truncation))
     band = {k for k, (sdf, w, rgb) in full.items() if np.any((w > 0) & (sdf != tau))}
-    assert band <= set(comp) and len(comp) < a.num_blocks  # blocks with a band (or an occluded) voxel
+    assert band == set(comp)
     for k, (sdf, w, rgb) in comp.items():
         s2, w2, c2 = full[k]
         assert np.array_equal(sdf, s2) and np.array_equal(w, w2) and np.array_equal(rgb, c2)
+    partial = 0
     for k, wk in zip(map(tuple, fk), fw):
         sdf, w, rgb = full[k]
         carved = w == 1
-        # weight 1 when the frame carved some voxel of the block, else unobserved
-        assert carved.any() == (wk == 1)
+        assert carved.all() == (wk == 1)
         assert np.all(sdf[carved] == tau) and np.all(w[~carved] == 0) and np.all(rgb == 0)
+        partial += bool(carved.any() and not carved.all())
+    assert partial > 10  # partly carved blocks stay unobserved
 
 
 @pytest.mark.parametrize("bits", [64, 32])
 def test_free_block_reads_tau_and_counts_frames(bits):
-    """A wall 1.4 m away seen n times: blocks wholly in front of it are free
-    blocks of weight n whose voxels read (tau, n); the voxel blocks at the
-    wall hold d - z in the band, as the per-voxel rule gives; free space
-    costs no voxel storage."""
+    """A wall 1.4 m away seen n times: blocks wholly in front of it and in
+    view are free blocks of weight n whose voxels read (tau, n), blocks the
+    frustum's sides cut are free blocks of weight 0 (unobserved); the voxel
+    blocks at the wall hold d - z in the band, as the per-voxel rule gives;
+    free space costs no voxel storage."""
     s, tau, d, n = 0.02, 0.06, 1.4, 5
     a, b = maps(s, tau, bits)
     fr = plane_frame(d)
     fuse(a, [fr] * n, [np.eye(4)] * n)
     fuse(b, [fr] * n, [np.eye(4)] * n)
     fk, fw = b.export_free()
-    assert len(fk) > 50 and np.all(fw == n)
+    assert (fw == n).sum() > 50 and set(np.unique(fw)) <= {0.0, float(n)}
     assert b.num_voxel_blocks + len(fk) == a.num_voxel_blocks  # free space costs no voxels
-    # free blocks read tau with weight n at every voxel (through the sampler)
-    for k in fk:
+    # free blocks read tau with weight n at every voxel (through the sampler);
+    # those of weight 0 read as unobserved
+    full = voxels_by_key(a)
+    for k, wk in zip(fk, fw):
         y = (8 * k.astype(np.float64) + 3.25) * float(np.float32(s))  # a cell inside the block
         ok, out = b.sample(y)
-        assert ok and out[0] == float(np.float32(tau)) and np.all(out[1:4] == 0)
+        assert ok == (wk == n)
+        if ok:
+            assert out[0] == float(np.float32(tau)) and np.all(out[1:4] == 0)
+        else:
+            assert not np.all(full[tuple(k)][1] == n)  # per-voxel carving did not carve it all
     # voxel blocks equal the per-voxel map (every voxel there was updated
     # identically: the same frame each time, blocks never switch)
-    full = voxels_by_key(a)
     for k, (sdf, w, rgb) in voxels_by_key(b).items():
         assert np.array_equal(sdf, full[k][0]) and np.array_equal(w, full[k][1])
     D = float(np.float32(d))
@@ -118,7 +126,8 @@ def test_moved_object_still_fades():
     """A wall at 0.9 m for 4 frames, then at 1.6 m: the voxels of the old
     wall decay toward tau by the running-average recurrence, whether their
     blocks are carved whole or voxel by voxel; free blocks in front of both
-    walls count all 7 frames."""
+    walls and wholly in view count all 7 frames, those behind the first wall
+    the last 3 or none."""
     s, tau = 0.02, 0.06
     _, b = maps(s, tau)
     near, far = plane_frame(0.9), plane_frame(1.6)
@@ -147,8 +156,12 @@ def test_moved_object_still_fades():
         checked += was_band.sum()
     assert checked > 100
     fk, fw = b.export_free()
-    front = A.block_voxel_centres(fk, s)[:, :, 2].max(1) < 0.9 - tau - 0.02
-    assert front.sum() > 10 and np.all(fw[front] == 7)
+    c = A.block_voxel_centres(fk, s)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        seen = np.all((c[:, :, 2] > 0) & (np.abs(30 * c[:, :, 0] / c[:, :, 2]) < 18)
+                      & (np.abs(30 * c[:, :, 1] / c[:, :, 2]) < 13), axis=1)
+    front = (c[:, :, 2].max(1) < 0.9 - tau - 0.02) & seen
+    assert front.sum() > 10 and np.all(fw[front] == 7) and set(np.unique(fw)) <= {0.0, 3.0, 7.0}
 
 
 def test_unmeasured_pixels_are_carved_over_masked_are_not():
@@ -206,35 +219,41 @@ def test_clipping_plane_bounds_free_space():
 def test_free_block_becomes_voxels_starting_from_its_value():
     """Free blocks in front of a wall at 1.6 m (3 frames), then a wall at
     1.2 m: the blocks the new wall cuts become voxel blocks whose voxels start
-    from (tau, 3), so a band voxel holds (3 tau + (d - z)) / 4 and weight 4."""
+    from their free value: from (tau, 3), so a band voxel holds
+    (3 tau + (d - z)) / 4 and weight 4, when all their voxels were carved in
+    each frame, and from unobserved, so a band voxel holds d - z and weight
+    1, when the frustum's sides cut them."""
     s, tau = 0.02, 0.06
     _, b = maps(s, tau)
     fuse(b, [plane_frame(1.6)] * 3, [np.eye(4)] * 3)
     fk3, fw3 = b.export_free()
-    free3 = {tuple(k) for k in fk3}
-    assert np.all(fw3 == 3)
+    assert set(np.unique(fw3)) <= {0.0, 3.0}
+    weight = {tuple(k): wk for k, wk in zip(fk3, fw3)}
     fuse(b, [plane_frame(1.2)], [np.eye(4)])
     keys, sdf, w, _ = b.export()
     cen = A.block_voxel_centres(keys, s)
     D, T = float(np.float32(1.2)), float(np.float32(tau))
-    checked = 0
+    checked = [0, 0]
     for i, k in enumerate(map(tuple, keys)):
-        if k not in free3:
+        if k not in weight:
             continue
         c = cen[i]
-        band = (np.abs(D - c[:, 2]) < tau - 1e-6) & (w[i] == 4)
-        ref = (3 * T + (D - c[:, 2])) / 4
+        n = int(weight[k])
+        band = (np.abs(D - c[:, 2]) < tau - 1e-6) & (w[i] == n + 1)
+        ref = (n * T + (D - c[:, 2])) / (n + 1)
         np.testing.assert_allclose(sdf[i][band], ref[band], rtol=0, atol=1e-15)
-        checked += band.sum()
-    assert checked > 50
+        checked[n == 3] += band.sum()
+    assert checked[0] > 20 and checked[1] > 50
 
 
 def test_block_behind_a_silhouette_keeps_its_occluded_voxels_unobserved():
     """A near half-plane (0.6 m, left) in front of a far one (1.6 m, right):
     blocks behind the near half's edge are carved through the right-hand
-    pixels and occluded through the left-hand ones.  Such a block must not
-    stay a free block (its value would stand for space behind a surface): it
-    holds voxels, occluded ones unobserved, exactly as per-voxel carving."""
+    pixels and occluded through the left-hand ones.  No voxel behind the
+    surface may read as free: such a block, unless a voxel of it is in the
+    band (then it holds exactly the per-voxel voxels), stays a free block of
+    weight 0, its carved voxels unrecorded, and reads as unobserved; seen
+    again from the side that carves it all, it counts that frame."""
     s, tau = 0.02, 0.06
     W, H, f = 40, 30, 30.0
     depth = np.full((H, W), 1.6, np.float32)
@@ -257,6 +276,29 @@ def test_block_behind_a_silhouette_keeps_its_occluded_voxels_unobserved():
         if occluded.any() and carved.any():
             mixed.append(k)
     assert len(mixed) > 3
+    fk, fw = b.export_free()
+    free_w = {tuple(q): wq for q, wq in zip(fk, fw)}
+    n_free = 0
     for k in mixed:
-        assert k in comp
-        assert np.array_equal(comp[k][1], full[k][1]) and np.array_equal(comp[k][0], full[k][0])
+        if k in comp:
+            assert np.array_equal(comp[k][1], full[k][1]) and np.array_equal(comp[k][0], full[k][0])
+        else:
+            assert free_w[k] == 0
+            y = (8 * np.array(k, np.float64) + 3.25) * float(np.float32(s))
+            assert not b.sample(y)[0]
+            n_free += 1
+    assert n_free > 3
+    # with the near half gone every voxel of those blocks is carved
+    far = O.Frame(np.full((H, W), 1.6, np.float32), rgb, f, f, (W - 1) / 2, (H - 1) / 2)
+    fuse(b, [far], [np.eye(4)])
+    fk, fw = b.export_free()
+    free_w = {tuple(q): wq for q, wq in zip(fk, fw)}
+    def wholly_carved(k):
+        c = A.block_voxel_centres(np.array([k]), s)[0]
+        if not np.all((c[:, 2] > 0) & (c[:, 2] < 1.6 - tau - 1e-3)):
+            return False
+        u = f * c[:, 0] / c[:, 2] + (W - 1) / 2
+        v = f * c[:, 1] / c[:, 2] + (H - 1) / 2
+        return bool(np.all((u > -0.4) & (u < W - 0.6) & (v > -0.4) & (v < H - 0.6)))
+    inner = [k for k in mixed if k not in comp and wholly_carved(k)]
+    assert len(inner) > 0 and all(free_w[k] == 1 for k in inner)
