@@ -36,7 +36,8 @@ rf_status check_launch(const char* what) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, mesh, cells, total;
+  size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, mesh, cells, wlist,
+      total;
   uint32_t dirty_cap, tc_tiles, cells_cap;
 };
 
@@ -84,6 +85,8 @@ Layout layout_of(const rf_map_params* p) {
   // pixels; ceil(W/8) ceil(H/8) <= W H / 64 + (W + H) / 8 + 1
   L.cells_cap = p->free_blocks ? p->max_pixels / 64 + (p->max_pixels + 1) / 8 + 2 : 0;
   L.cells = o; o = align256(o + (size_t)L.cells_cap * 4);
+  // compact free space: the integration's work list (one entry per bucket at most)
+  L.wlist = o; o = align256(o + (p->free_blocks ? (size_t)p->num_buckets * 4 : 0));
   L.total = o;
   return L;
 }
@@ -255,6 +258,7 @@ rf_status hashmap_create(const rf_map_params* p, void* arena, size_t bytes, void
   d.cells = reinterpret_cast<float*>(a + L.cells);
   d.cells_cap = L.cells_cap;
   d.free_blocks = p->free_blocks ? 1u : 0u;
+  d.wlist = p->free_blocks ? reinterpret_cast<uint32_t*>(a + L.wlist) : nullptr;
   d.dirty = reinterpret_cast<uint32_t*>(a + L.dirty);
   d.tcache = reinterpret_cast<rf::BlockRef*>(a + L.tcache);
   d.tc_count = reinterpret_cast<uint32_t*>(a + L.tc_count);

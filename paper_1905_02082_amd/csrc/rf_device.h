@@ -13,6 +13,7 @@
 //                then kCacheLevels x tc_tiles x 4 B pair counts
 //   mesh scratch 2 x kMeshScratch x 4 B
 //   cells        compact free space only: per 8x8 pixel cell of the frame, its smallest measured depth
+//   wlist        compact free space only: num_buckets x 4 B, the integration's work list
 //
 // Hash: key = three 21-bit biased block coordinates; bucket = hash3 & mask,
 // linear probing, insertion by 64-bit CAS on the key word (insert-only: keys
@@ -101,6 +102,8 @@ struct DevState {
   unsigned long long cum_blocks;  // since create/reset: listed blocks integrated
   unsigned long long cum_frames;  // since create/reset: integrations
   unsigned long long cum_whole;   // since create/reset: listed blocks carved whole (compact free space)
+  uint32_t w_count;        // compact free space: entries in wlist
+  uint32_t n_whole;        // compact free space: listed blocks carved whole by the running integration
 };
 
 // Starts a new allocation epoch: 0 is the stamp of a bucket never touched,
@@ -123,11 +126,13 @@ struct MapDev {
   DevState* st;
   double* partials;
   uint8_t* md;
-  uint4* integ_counts;  // per integration workgroup: (band, free, blocks carved whole, 0) of the last integration
+  uint4* integ_counts;  // per integration workgroup: (band, free, 0, 0) updates of the last integration
   float* cells;         // compact free space: per 8x8 pixel cell of the frame being integrated, the
                         // smallest measured depth (0 if a pixel is masked or none is measured)
   uint32_t cells_cap;
   uint32_t free_blocks; // 1: compact free space
+  uint32_t* wlist;      // compact free space: the frame-list entries left to the integration once the
+                        // free blocks carved whole are counted (flist_cap entries)
   BlockRef* tcache;     // tracking block cache (per level: tc_tiles tiles of tile_refs(level) pairs)
   uint32_t* tc_count;   // valid pairs of each cached tile (kCacheLevels x tc_tiles)
   uint32_t* mesh_scratch;  // mesh extraction: triangles and offsets per workgroup (2 x kMeshScratch)

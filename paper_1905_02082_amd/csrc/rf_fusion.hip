@@ -282,11 +282,13 @@ __global__ void reset_frame_list_kernel(Batch b) {
 // carve every voxel of such a block; unmeasured pixels are carved over.
 //
 // A free block (no voxels, bucket slot kFreeSlot | count) carved whole only
-// counts the frame.  A free block not carved whole takes a pool slot here and
-// is integrated voxel by voxel from its value (tau and its count, or
-// unobserved while the count is 0).  A block of voxels carved whole gives
-// every voxel the free-space update without projecting it.  The outcome of
-// each listed block goes into bits 22-31 of its frame-list entry (bucket
+// counts the frame, here, and is left out of the integration's work list.
+// A free block not carved whole is evaluated by the integration voxel by
+// voxel from its value (tau and its count, or unobserved while the count is
+// 0): a band update gives it a pool slot, a frame that carves all of its
+// voxels counts for it, any other frame leaves it as it is.  A block of
+// voxels carved whole gives every voxel the free-space update without
+// projecting it.  Work-list entries carry the outcome in bits 22-31 (bucket
 // indices stay below 2^22).
 constexpr uint32_t kEntryBucket = 0x003FFFFFu;
 constexpr uint32_t kEntryWhole = 0x80000000u;  // carved whole
@@ -296,30 +298,35 @@ constexpr float kCarveMargin = 1.0e-3f;        // metres
 constexpr int kMaxTestCells = 64;
 constexpr int kClassifyGroups = 512;           // workgroups of the whole-block test (all jobs together)
 
+// One wavefront per 8x8 cell (lane = pixel), four cells per workgroup.  The
+// first workgroup of a job also starts the frame's work list and its count
+// of blocks carved whole (classify_kernel runs after it on the stream).
+constexpr int kCellsPerGroup = 4;
+
 template <int DF>
 __global__ __launch_bounds__(256) void depth_cells_kernel(Batch b) {
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const FrameDev& f = J.f;
-  const int c = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
-  if (c >= J.cells_w * J.cells_h) return;
-  const int u0 = (c % J.cells_w) * kCell, v0 = (c / J.cells_w) * kCell;
-  const uint8_t* mask = J.mask;
-  float e = INFINITY;
-  bool masked = false;
-  for (int dv = 0; dv < kCell; ++dv) {
-    const int v = v0 + dv;
-    if (v >= f.H) break;
-    for (int du = 0; du < kCell; ++du) {
-      const int u = u0 + du;
-      if (u >= f.W) break;
-      const int idx = v * f.W + u;
-      const float D = load_depth<DF>(f, idx);
-      masked = masked || (mask && mask[idx]);
-      if (D > 0.0f) e = fminf(e, D);
-    }
+  const int g = blockIdx.x - b.base[jb];
+  if (g == 0 && threadIdx.x == 0) {
+    J.m.st->w_count = 0;
+    J.m.st->n_whole = 0;
   }
-  J.m.cells[c] = (masked || e == INFINITY) ? 0.0f : e;
+  const int c = g * kCellsPerGroup + (int)(threadIdx.x >> 6);
+  if (c >= J.cells_w * J.cells_h) return;  // uniform per wavefront
+  const int lane = threadIdx.x & 63;
+  const int u = (c % J.cells_w) * kCell + (lane & 7), v = (c / J.cells_w) * kCell + (lane >> 3);
+  const bool in = u < f.W && v < f.H;
+  const int idx = in ? v * f.W + u : 0;
+  const float D = in ? load_depth<DF>(f, idx) : 0.0f;
+  const uint8_t* mask = J.mask;
+  const bool masked = in && mask && mask[idx];
+  float e = (D > 0.0f) ? D : INFINITY;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e = fminf(e, __shfl_xor(e, o));
+  const bool any_masked = __ballot(masked) != 0ull;
+  if (lane == 0) J.m.cells[c] = (any_masked || e == INFINITY) ? 0.0f : e;
 }
 
 __device__ __forceinline__ bool carved_whole(const MapDev& m, const FrameDev& f, const Job& J, const float R[9],
@@ -366,24 +373,51 @@ __global__ __launch_bounds__(256) void classify_kernel(Batch b) {
   float R[9], t[3];
   load_pose_f(J.pose, R, t);
   const uint32_t wmax = (uint32_t)m.max_weight;
-  for (uint32_t i = g0 * blockDim.x + threadIdx.x; i < nF; i += gn * blockDim.x) {
-    const uint32_t e = m.flist[i] & kEntryBucket;
-    const Bucket bk = m.buckets[e];
-    int bx, by, bz;
-    unpack_key(bk.key, bx, by, bz);
-    const bool whole = carved_whole(m, f, J, R, t, bx, by, bz);
-    uint32_t entry = e | (whole ? kEntryWhole : 0u);
-    if (is_free_slot(bk.slot)) {
-      const uint32_t c = bk.slot & 0xFFu;
-      if (whole) {
-        m.buckets[e].slot = kFreeSlot | min(c + 1u, wmax);
-        entry |= kEntryFresh;  // whole + free: a free block carved whole, nothing left to do
-      } else {
-        entry |= kEntryFresh | (c << kEntryCountShift);  // free: decided voxel by voxel
+  const int lane = threadIdx.x & 63;
+  uint32_t n_whole = 0;
+  // uniform trip count per workgroup, so every wavefront reaches the ballots
+  const uint32_t step = gn * blockDim.x;
+  for (uint32_t i0 = g0 * blockDim.x; i0 < nF; i0 += step) {
+    const uint32_t i = i0 + threadIdx.x;
+    bool work = false;
+    uint32_t entry = 0;
+    if (i < nF) {
+      const uint32_t e = m.flist[i] & kEntryBucket;
+      const Bucket bk = m.buckets[e];
+      int bx, by, bz;
+      unpack_key(bk.key, bx, by, bz);
+      const bool whole = carved_whole(m, f, J, R, t, bx, by, bz);
+      n_whole += whole;
+      entry = e | (whole ? kEntryWhole : 0u);
+      work = true;
+      if (is_free_slot(bk.slot)) {
+        const uint32_t c = bk.slot & 0xFFu;
+        if (whole) {
+          m.buckets[e].slot = kFreeSlot | min(c + 1u, wmax);
+          work = false;  // a free block carved whole: counted, nothing left to do
+        } else {
+          entry |= kEntryFresh | (c << kEntryCountShift);  // free: decided voxel by voxel
+        }
       }
     }
-    m.flist[i] = entry;
+    // the entries left to the integration go to the work list, one atomic
+    // per wavefront
+    const unsigned long long bal = __ballot(work);
+    if (bal != 0ull) {  // uniform
+      const int leader = __ffsll((long long)bal) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&m.st->w_count, (uint32_t)__popcll(bal));
+      base = __shfl(base, leader);
+      const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (work && base + pre < m.flist_cap) m.wlist[base + pre] = entry;
+    }
   }
+  __shared__ uint32_t s_whole;
+  if (threadIdx.x == 0) s_whole = 0;
+  __syncthreads();
+  if (n_whole) atomicAdd(&s_whole, n_whole);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_whole) atomicAdd(&m.st->n_whole, s_whole);
 }
 
 // Integration of one frame into the blocks of the frame list (Sec. III-A
@@ -431,10 +465,14 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   const uint8_t* mask = J.mask;
   const uint8_t* mask_src = mask ? mask : f.rgb;  // a readable plane when there is no mask
   const uint32_t g0 = blockIdx.x - b.base[jb], gn = b.base[jb + 1] - b.base[jb];
-  const uint32_t nF = min(m.st->f_count, m.flist_cap);
+  // compact free-space maps work on the entries classify_kernel left (free
+  // blocks carved whole are done), the others on the whole frame list
+  const bool wl = COMPACT && m.free_blocks;
+  const uint32_t* list = wl ? m.wlist : m.flist;
+  const uint32_t nF = min(wl ? m.st->w_count : m.st->f_count, m.flist_cap);
   float R[9], t[3];
   load_pose_f(J.pose, R, t);
-  uint32_t nb = 0, nf = 0, nw = 0;
+  uint32_t nb = 0, nf = 0;
   const uint32_t stride = kIntegBlocks * gn;
   // correctly rounded reciprocals 1 / (W + 1) of the weights 0 .. 255
   __shared__ float s_rw[256];
@@ -455,15 +493,15 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   // step starts without waiting for those stores.
   const int lane = threadIdx.x & 63;
   const uint32_t my_i = (uint32_t)min(lane, kIntegBlocks - 1);
-  // frame-list entries of compact free-space maps carry the whole-block
+  // work-list entries of compact free-space maps carry the whole-block
   // test's outcome in their top bits (compact maps keep bucket indices below
-  // 2^22); other maps' entries are plain bucket indices
-  const uint32_t bucket_bits = (COMPACT && m.free_blocks) ? kEntryBucket : 0xFFFFFFFFu;
+  // 2^22); frame-list entries are plain bucket indices
+  const uint32_t bucket_bits = wl ? kEntryBucket : 0xFFFFFFFFu;
   Bucket cur[kIntegBlocks];
   uint32_t cur_e[kIntegBlocks];
   if (g0 < nF) {
     const uint32_t fi = g0 + my_i * gn;
-    const uint32_t e = m.flist[fi < nF ? fi : g0];
+    const uint32_t e = list[fi < nF ? fi : g0];
     const Bucket bq = m.buckets[e & bucket_bits];
     take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
     take_state<kIntegBlocks>(e, cur_e);
@@ -479,17 +517,16 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       st[i] = COMPACT ? (cur_e[i] & ~bucket_bits) : 0u;
       eb[i] = cur_e[i] & bucket_bits;
       whole[i] = (st[i] & kEntryWhole) != 0u;
-      // a free block not carved whole: evaluated voxel by voxel from its
-      // free value, it takes a pool slot below if a voxel gets a band update
+      // a free block: evaluated voxel by voxel from its free value, it takes
+      // a pool slot below if a voxel gets a band update
       pend[i] = (st[i] & (kEntryWhole | kEntryFresh)) == kEntryFresh;
-      // a free block carved whole has nothing left to update
-      live[i] = f0 + i * gn < nF && (bu[i].slot < m.max_blocks || pend[i]) && !(whole[i] && (st[i] & kEntryFresh));
+      live[i] = f0 + i * gn < nF && (bu[i].slot < m.max_blocks || pend[i]);
     }
     // the next step's list entries (past the list's end: this step's first
     // entry again, so the loads stay unconditional and in bounds)
     const uint32_t f1 = f0 + stride;
     const uint32_t fn = f1 + my_i * gn;
-    const uint32_t hn = m.flist[fn < nF ? fn : f0];
+    const uint32_t hn = list[fn < nF ? fn : f0];
     int pix[NV];
     uint32_t vidx[NV];
     float X2[NV];
@@ -665,8 +702,6 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
     take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
     take_state<kIntegBlocks>(hn, cur_e);
 #pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) nw += (whole[i] && f0 + i * gn < nF) ? 1u : 0u;
-#pragma unroll
     for (int v = 0; v < NV; ++v) {
       if (!band[v]) continue;
       const float Wv = W[v], Wn = W[v] + 1.0f;
@@ -687,8 +722,7 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   if (nb) atomicAdd(&s_cnt[0], nb);
   if (nf) atomicAdd(&s_cnt[1], nf);
   __syncthreads();
-  // nw is uniform over the workgroup (every thread counts the same blocks)
-  if (threadIdx.x == 0) m.integ_counts[g0] = make_uint4(s_cnt[0], s_cnt[1], nw, 0u);
+  if (threadIdx.x == 0) m.integ_counts[g0] = make_uint4(s_cnt[0], s_cnt[1], 0u, 0u);
 }
 
 // One workgroup per job: the integration's per-workgroup counts into the
@@ -697,23 +731,20 @@ __global__ __launch_bounds__(256) void integ_fold_kernel(Batch b) {
   const Job& J = b.job[blockIdx.x];
   const MapDev& m = J.m;
   const int ng = b.base[blockIdx.x + 1] - b.base[blockIdx.x];
-  unsigned long long band = 0, free = 0, whole = 0;
+  unsigned long long band = 0, free = 0;
   for (int i = threadIdx.x; i < ng; i += blockDim.x) {
     const uint4 c = m.integ_counts[i];
     band += c.x;
     free += c.y;
-    whole += c.z;
   }
-  __shared__ unsigned long long s_b[256], s_f[256], s_w[256];
+  __shared__ unsigned long long s_b[256], s_f[256];
   s_b[threadIdx.x] = band;
   s_f[threadIdx.x] = free;
-  s_w[threadIdx.x] = whole;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       s_b[threadIdx.x] += s_b[threadIdx.x + w];
       s_f[threadIdx.x] += s_f[threadIdx.x + w];
-      s_w[threadIdx.x] += s_w[threadIdx.x + w];
     }
     __syncthreads();
   }
@@ -725,10 +756,13 @@ __global__ __launch_bounds__(256) void integ_fold_kernel(Batch b) {
     st->cum_free += s_f[0];
     st->cum_blocks += min(st->f_count, m.flist_cap);
     st->cum_frames += 1;
-    st->cum_whole += s_w[0];
-    // compact free space: free blocks changed their counts or took pool
-    // slots, so tracking caches must not keep their old slot codes
-    if (m.free_blocks) advance_epoch(st);
+    if (m.free_blocks) {
+      // blocks carved whole, counted by classify_kernel
+      st->cum_whole += st->n_whole;
+      // free blocks changed their counts or took pool slots, so tracking
+      // caches must not keep their old slot codes
+      advance_epoch(st);
+    }
   }
 }
 
@@ -759,7 +793,7 @@ void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
   bool compact = false;
   for (int j = 0; j < b.n; ++j) {
     b.base[j] = cells;
-    cells += (b.job[j].cells_w * b.job[j].cells_h + 255) / 256;
+    cells += (b.job[j].cells_w * b.job[j].cells_h + kCellsPerGroup - 1) / kCellsPerGroup;
     compact = compact || b.job[j].m.free_blocks;
   }
   b.base[b.n] = cells;

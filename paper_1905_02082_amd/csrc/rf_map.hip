@@ -38,6 +38,8 @@ __global__ void init_state_kernel(DevState* st) {
     st->cum_frames = 0;
     st->cum_whole = 0;
     st->n_keys = 0;
+    st->w_count = 0;
+    st->n_whole = 0;
   }
 }
 
