@@ -89,10 +89,12 @@ typedef struct {
   uint32_t max_pixels;    /* largest width*height passed to compute_dynamic_mask */
   int32_t free_blocks;    /* 1: compact free space (the free-space representation Sec. III-D leaves to
                              future work, as coarse free-block flags): a listed block whose image
-                             rectangle holds only depths beyond it (+tau) is carved whole; a block only
-                             ever carved whole keeps no voxels, its 512 voxels read as (sdf tau,
-                             weight = frames that carved it, colour 0), and it takes a pool slot the
-                             first time a frame does not carve it whole.  Needs num_buckets <= 2^22.
+                             rectangle holds only depths beyond it (+tau) is carved whole; a new block
+                             keeps no voxels (a free block), its 512 voxels read as (sdf tau, weight =
+                             frames that carved all of them, colour 0; unobserved while 0); it takes a
+                             pool slot, its voxels starting from that value, the first time one of its
+                             voxels gets a band update, and a frame that carves only some of its voxels
+                             leaves it as it is.  Needs num_buckets <= 2^22.
                              0: every voxel carved by the per-voxel rule (Sec. III-D as written). */
 } rf_map_params;
 

@@ -216,11 +216,12 @@ struct Voxel {
 
 // Compact free space (P.free_blocks = 1; the octree or free-space
 // representation that Sec. III-D leaves to future work, read here as coarse
-// free-block flags): a block that has only ever been carved whole is a free
-// block, kept as one voxel value (sdf tau, weight = the number of frames that
-// carved it, capped; unobserved while that is 0) that every one of its 512
-// voxels reads as.  It becomes an ordinary block of voxels, all starting from
-// that value, the first time a frame does not carve it whole.
+// free-block flags): a new block is a free block, kept as one voxel value
+// (sdf tau, weight = the number of frames that carved all of its voxels,
+// capped; unobserved while that is 0) that every one of its 512 voxels reads
+// as.  It becomes an ordinary block of voxels, all starting from that value,
+// the first time one of its voxels gets a band update; a frame that carves
+// only some of its voxels leaves it as it is.
 template <class Real>
 struct Map : MapBase {
   std::unordered_map<Key, std::vector<Voxel<Real>>, KeyHash> blocks;
