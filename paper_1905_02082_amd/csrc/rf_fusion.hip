@@ -30,9 +30,10 @@ namespace rf {
 __device__ __forceinline__ bool leads_run(unsigned long long key, bool valid, unsigned long long active) {
   const int lane = threadIdx.x & 63;
   const unsigned long long vmask = __ballot(valid) & active;
-  const int src = lane > 0 ? lane - 1 : 0;
-  const unsigned int klo = (unsigned int)__shfl((int)(unsigned int)key, src, 64);
-  const unsigned int khi = (unsigned int)__shfl((int)(unsigned int)(key >> 32), src, 64);
+  // lane - 1's key, moved by a wavefront shift (DPP) rather than an LDS
+  // permute; lane 0 and lanes whose neighbour is not valid ignore it
+  const unsigned int klo = __builtin_amdgcn_update_dpp(0u, (unsigned int)key, 0x138, 0xF, 0xF, false);
+  const unsigned int khi = __builtin_amdgcn_update_dpp(0u, (unsigned int)(key >> 32), 0x138, 0xF, 0xF, false);
   const bool below_same = lane > 0 && ((vmask >> (lane - 1)) & 1ull) &&
                           ((((unsigned long long)khi << 32) | klo) == key);
   return valid && !below_same;
@@ -630,7 +631,10 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
     bool fresh[kIntegBlocks];
 #pragma unroll
     for (int i = 0; i < kIntegBlocks; ++i) fresh[i] = false;
-    if (COMPACT && (pend[0] || pend[1])) {  // uniform
+    bool any_pend = false;
+#pragma unroll
+    for (int i = 0; i < kIntegBlocks; ++i) any_pend = any_pend || pend[i];
+    if (COMPACT && any_pend) {  // uniform
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         if (pend[v >> 1] && live[v >> 1] && (band[v] || !upd[v])) atomicOr(&s_pf[v >> 1], band[v] ? 1u : 2u);
