@@ -215,7 +215,7 @@ __device__ __forceinline__ int insert_block(const MapDev& m, int x, int y, int z
         atomicAdd(&m.st->n_keys, 1u);
         uint32_t slot;
         if (m.free_blocks) {
-          slot = kFreeSlot;  // a free block: no voxels until a frame does not carve it whole
+          slot = kFreeSlot;  // a free block: no voxels until one of them gets a band update
         } else {
           slot = atomicAdd(&m.st->n_blocks, 1u);
           if (slot < m.max_blocks) {

@@ -3,11 +3,12 @@
 //
 // Allocation: one thread per pixel walks the block grid along its band (or
 // carve) segment with a DDA; each visited block is inserted into the hash by
-// CAS and, the first time it is touched in this frame (per-bucket frame
-// stamp, exchanged atomically), appended to the frame's block list (through
-// a per-workgroup list in LDS).  Carve rays run in workgroups of their own;
-// cells are probed 12 at a time, with their bucket loads, stamp exchanges and
-// list appends each issued together.
+// CAS and its bucket stamped with the frame's epoch by a plain store (every
+// ray that touches it stores the same value, so no exchange is needed).
+// Carve rays run in workgroups of their own; cells are probed 12 at a time,
+// with their bucket loads and stamp stores each issued together.  A second
+// kernel then lists the buckets stamped with the epoch: the frame's block
+// list, each touched block once.
 //
 // Integration: workgroups stride over the listed blocks, 256 threads x 2
 // voxels per block, two blocks per step, the next step's list entries and
@@ -89,15 +90,10 @@ struct Dda {
   }
 };
 
-// Capacity of a workgroup's list of first touches in LDS; first touches
-// beyond it go to the frame list directly.
-constexpr uint32_t kAllocList = 2048;
-
 // One thread's ray: its cells' blocks are inserted if absent and stamped with
-// the frame; the first touches are appended to the workgroup's list s_list
-// (s_n entries, LDS), or past its capacity to the frame list.
+// the frame's epoch.
 template <int DF>
-__device__ __forceinline__ void alloc_ray(const Job& J, int g, uint32_t* s_list, uint32_t* s_n) {
+__device__ __forceinline__ void alloc_ray(const Job& J, int g) {
   const MapDev& m = J.m;
   const FrameDev& f = J.f;
   int u, v;
@@ -172,59 +168,15 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g, uint32_t* s_list,
       hb[q] = hash3(cx[q], cy[q], cz[q]) & m.bucket_mask;
       bk[q] = m.buckets[hb[q]];
     }
-    // Stamp every cell's bucket with the frame (exchanges issued together);
-    // the cells whose old stamp differed are this frame's first touches.
-    uint32_t old[kBatch];
-    int hq[kBatch];
+    // Stamp every cell's bucket with the frame (stores issued together); an
+    // absent block is inserted first
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
-      old[q] = frame_id;
-      hq[q] = -1;
       if (!ok[q]) continue;
-      if (bk[q].key == key[q]) {
-        hq[q] = (int)hb[q];
-        if (bk[q].stamp != frame_id) old[q] = atomicExch(&m.buckets[hb[q]].stamp, frame_id);
-      } else {
-        hq[q] = insert_block(m, cx[q], cy[q], cz[q]);
-        if (hq[q] >= 0) old[q] = atomicExch(&m.buckets[hq[q]].stamp, frame_id);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kBatch; ++q) asm volatile("" : "+v"(old[q]));
-    // First touches are appended to the workgroup's list with one LDS atomic
-    // per wavefront and batch (ballot + mbcnt give each its position).
-    const int lane = threadIdx.x & 63;
-    uint32_t tot = 0, off[kBatch];
-    bool first[kBatch];
-#pragma unroll
-    for (int q = 0; q < kBatch; ++q) {
-      first[q] = hq[q] >= 0 && old[q] != frame_id;
-      const unsigned long long bq = __ballot(first[q]);
-      off[q] = tot + __builtin_amdgcn_mbcnt_hi((uint32_t)(bq >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bq, 0u));
-      tot += (uint32_t)__popcll(bq);
-    }
-    if (tot) {
-      const int leader = __ffsll((long long)__ballot(true)) - 1;
-      uint32_t pos = 0;
-      if (lane == leader) pos = atomicAdd(s_n, tot);  // LDS
-      pos = __builtin_amdgcn_readlane(pos, leader);
-      // entries from position kAllocList on go to the frame list directly
-      const uint32_t lo = pos > kAllocList ? pos : kAllocList;
-      const uint32_t n_over = pos + tot > lo ? pos + tot - lo : 0u;
-      uint32_t gbase = 0;
-      if (n_over && lane == leader) gbase = atomicAdd(&m.st->f_count, n_over);
-      gbase = __builtin_amdgcn_readlane(gbase, leader);
-#pragma unroll
-      for (int q = 0; q < kBatch; ++q) {
-        if (!first[q]) continue;
-        const uint32_t i = pos + off[q];
-        if (i < kAllocList) {
-          s_list[i] = (uint32_t)hq[q];
-        } else {
-          const uint32_t k = gbase + (i - lo);
-          if (k < m.flist_cap) m.flist[k] = (uint32_t)hq[q];
-        }
-      }
+      int h = (int)hb[q];
+      if (bk[q].key != key[q]) h = insert_block(m, cx[q], cy[q], cz[q]);
+      else if (bk[q].stamp == frame_id) continue;
+      if (h >= 0) m.buckets[h].stamp = frame_id;
     }
   }
 }
@@ -234,25 +186,72 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
   // Per job: workgroups [0, carve_groups) take the carve segments of the
   // carve-grid pixels, the rest the band segments of the other pixels, so the
   // long rays share wavefronts with rays of similar length; the carve
-  // workgroups come first so that the longest chains start first.  A
-  // workgroup gathers its first touches in LDS and appends them to the frame
-  // list with one counter atomic at its end (one per wavefront and batch had
-  // made the counter's single address the bottleneck).
-  __shared__ uint32_t s_list[kAllocList];
+  // workgroups come first so that the longest chains start first.
+  const int jb = batch_job(b, blockIdx.x);
+  alloc_ray<DF>(b.job[jb], blockIdx.x - b.base[jb]);
+}
+
+// The frame's block list: every bucket stamped with the epoch, appended in
+// runs gathered per workgroup in LDS (one counter atomic per workgroup and
+// run; the order of the list is not fixed, its content is).  One workgroup
+// per CU and job streams a contiguous range of buckets.
+constexpr int kListGroups = 256;   // workgroups of the listing (all jobs together)
+constexpr uint32_t kListRun = 2048;
+
+__global__ __launch_bounds__(256) void list_frame_kernel(Batch b) {
+  __shared__ uint32_t s_run[kListRun];
   __shared__ uint32_t s_n, s_base;
   const int jb = batch_job(b, blockIdx.x);
-  const Job& J = b.job[jb];
-  const MapDev& m = J.m;
+  const MapDev& m = b.job[jb].m;
+  const uint32_t nb = m.bucket_mask + 1u;
+  const uint32_t epoch = m.st->epoch;
+  const uint32_t g0 = blockIdx.x - b.base[jb], gn = b.base[jb + 1] - b.base[jb];
+  const uint32_t per = (nb + gn - 1) / gn;
+  const uint32_t h0 = g0 * per, h1 = min(h0 + per, nb);
+  const int lane = threadIdx.x & 63;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  alloc_ray<DF>(J, blockIdx.x - b.base[jb], s_list, &s_n);
+  for (uint32_t c0 = h0; c0 < h1; c0 += 4 * blockDim.x) {  // uniform
+    // four buckets per thread in flight
+    bool hit[4];
+    uint32_t hh[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      hh[r] = c0 + r * blockDim.x + threadIdx.x;
+      hit[r] = false;
+      if (hh[r] < h1) {
+        const Bucket bk = m.buckets[hh[r]];
+        hit[r] = bk.key != kEmptyKey && bk.stamp == epoch;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const unsigned long long bal = __ballot(hit[r]);
+      if (bal == 0ull) continue;  // uniform
+      const int leader = __ffsll((long long)bal) - 1;
+      uint32_t pos = 0;
+      if (lane == leader) pos = atomicAdd(&s_n, (uint32_t)__popcll(bal));  // LDS
+      pos = __shfl(pos, leader);
+      const uint32_t i = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (hit[r]) {
+        if (i < kListRun) {
+          s_run[i] = hh[r];
+        } else {
+          // past the run's capacity: straight to the frame list
+          const uint32_t k = atomicAdd(&m.st->f_count, 1u);
+          if (k < m.flist_cap) m.flist[k] = hh[r];
+        }
+      }
+    }
+  }
   __syncthreads();
-  const uint32_t n = min(s_n, kAllocList);
+  const uint32_t n = min(s_n, kListRun);
   if (threadIdx.x == 0) s_base = n ? atomicAdd(&m.st->f_count, n) : 0u;
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
     const uint32_t k = s_base + i;
-    if (k < m.flist_cap) m.flist[k] = s_list[i];
+    if (k < m.flist_cap) m.flist[k] = s_run[i];
   }
 }
 
@@ -787,6 +786,9 @@ void launch_allocate(Batch& b, int depth_format, hipStream_t s) {
   b.base[b.n] = total;
   if (depth_format == RF_DEPTH_U16) alloc_kernel<RF_DEPTH_U16><<<total, 256, 0, s>>>(b);
   else alloc_kernel<RF_DEPTH_F32><<<total, 256, 0, s>>>(b);
+  const int per = kListGroups / b.n;
+  for (int j = 0; j <= b.n; ++j) b.base[j] = j * per;
+  list_frame_kernel<<<b.n * per, 256, 0, s>>>(b);
 }
 
 void launch_integrate(Batch& b, int depth_format, int storage, hipStream_t s) {
