@@ -203,11 +203,13 @@ __device__ __forceinline__ int resolve_slot(const MapDev& m, Bucket b, unsigned 
 }
 
 // Inserts block (x,y,z) if absent; returns its bucket index or -1 (hash full).
-__device__ __forceinline__ int insert_block(const MapDev& m, int x, int y, int z) {
+// Probe from bucket h, whose key k the caller has already read, for block
+// (x,y,z); insert it at the first empty bucket if absent.
+__device__ __forceinline__ int find_or_insert_from(const MapDev& m, int x, int y, int z, uint32_t h,
+                                                   unsigned long long k) {
   const unsigned long long key = pack_key(x, y, z);
-  uint32_t h = hash3(x, y, z) & m.bucket_mask;
   for (uint32_t i = 0; i < m.max_probe; ++i) {
-    unsigned long long k = m.buckets[h].key;
+    if (i > 0) k = m.buckets[h].key;
     if (k == key) return (int)h;
     if (k == kEmptyKey) {
       unsigned long long old = atomicCAS(&m.buckets[h].key, kEmptyKey, key);
@@ -234,6 +236,11 @@ __device__ __forceinline__ int insert_block(const MapDev& m, int x, int y, int z
   }
   atomicOr(&m.st->flags, (uint32_t)RF_FLAG_HASH_FULL);
   return -1;
+}
+
+__device__ __forceinline__ int insert_block(const MapDev& m, int x, int y, int z) {
+  const uint32_t h = hash3(x, y, z) & m.bucket_mask;
+  return find_or_insert_from(m, x, y, z, h, m.buckets[h].key);
 }
 
 // ---------------------------------------------------------------- storage

@@ -168,14 +168,28 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
       hb[q] = hash3(cx[q], cy[q], cz[q]) & m.bucket_mask;
       bk[q] = m.buckets[hb[q]];
     }
+    // Cells whose home bucket holds another block: the next bucket's key,
+    // loaded for all of them together (linear probing puts most displaced
+    // blocks there), before any probes on.
+    unsigned long long k1[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      k1[q] = kEmptyKey;
+      if (ok[q] && bk[q].key != key[q] && bk[q].key != kEmptyKey) k1[q] = m.buckets[(hb[q] + 1u) & m.bucket_mask].key;
+    }
     // Stamp every cell's bucket with the frame (stores issued together); an
     // absent block is inserted first
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
       if (!ok[q]) continue;
       int h = (int)hb[q];
-      if (bk[q].key != key[q]) h = insert_block(m, cx[q], cy[q], cz[q]);
-      else if (bk[q].stamp == frame_id) continue;
+      if (bk[q].key == key[q]) {
+        if (bk[q].stamp == frame_id) continue;
+      } else if (bk[q].key != kEmptyKey && k1[q] == key[q]) {
+        h = (int)((hb[q] + 1u) & m.bucket_mask);
+      } else {
+        h = find_or_insert_from(m, cx[q], cy[q], cz[q], hb[q], bk[q].key);
+      }
       if (h >= 0) m.buckets[h].stamp = frame_id;
     }
   }
