@@ -238,6 +238,31 @@ __device__ __forceinline__ int find_or_insert_from(const MapDev& m, int x, int y
   return -1;
 }
 
+// As find_or_insert_from, but a block this call inserts gets no pool slot
+// and is not counted here (*claimed is set): the caller assigns slots and
+// counts for a whole wavefront at once (one counter atomic instead of one
+// per new block).
+__device__ __forceinline__ int find_or_claim_from(const MapDev& m, int x, int y, int z, uint32_t h,
+                                                  unsigned long long k, bool* claimed) {
+  const unsigned long long key = pack_key(x, y, z);
+  *claimed = false;
+  for (uint32_t i = 0; i < m.max_probe; ++i) {
+    if (i > 0) k = m.buckets[h].key;
+    if (k == key) return (int)h;
+    if (k == kEmptyKey) {
+      const unsigned long long old = atomicCAS(&m.buckets[h].key, kEmptyKey, key);
+      if (old == kEmptyKey) {
+        *claimed = true;
+        return (int)h;
+      }
+      if (old == key) return (int)h;
+    }
+    h = (h + 1) & m.bucket_mask;
+  }
+  atomicOr(&m.st->flags, (uint32_t)RF_FLAG_HASH_FULL);
+  return -1;
+}
+
 __device__ __forceinline__ int insert_block(const MapDev& m, int x, int y, int z) {
   const uint32_t h = hash3(x, y, z) & m.bucket_mask;
   return find_or_insert_from(m, x, y, z, h, m.buckets[h].key);

@@ -179,8 +179,12 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
     }
     // Stamp every cell's bucket with the frame (stores issued together); an
     // absent block is inserted first
+    int hq[kBatch];
+    bool claimed[kBatch];
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
+      hq[q] = -1;
+      claimed[q] = false;
       if (!ok[q]) continue;
       int h = (int)hb[q];
       if (bk[q].key == key[q]) {
@@ -188,9 +192,38 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
       } else if (bk[q].key != kEmptyKey && k1[q] == key[q]) {
         h = (int)((hb[q] + 1u) & m.bucket_mask);
       } else {
-        h = find_or_insert_from(m, cx[q], cy[q], cz[q], hb[q], bk[q].key);
+        h = find_or_claim_from(m, cx[q], cy[q], cz[q], hb[q], bk[q].key, &claimed[q]);
       }
+      hq[q] = h;
       if (h >= 0) m.buckets[h].stamp = frame_id;
+    }
+    // The blocks this batch inserted: key counts and pool slots (compact
+    // free-space maps: none) with one counter atomic per wavefront and cell.
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const unsigned long long bal = __ballot(claimed[q]);
+      if (bal == 0ull) continue;  // uniform
+      const int leader = __ffsll((long long)bal) - 1;
+      const uint32_t cnt = (uint32_t)__popcll(bal);
+      uint32_t base = 0;
+      if (lane == leader) {
+        atomicAdd(&m.st->n_keys, cnt);
+        if (!m.free_blocks) base = atomicAdd(&m.st->n_blocks, cnt);
+      }
+      base = __shfl(base, leader);
+      if (!claimed[q]) continue;
+      uint32_t slot = kFreeSlot;  // a free block: no voxels until one of them gets a band update
+      if (!m.free_blocks) {
+        slot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (slot < m.max_blocks) {
+          m.block_keys[slot] = key[q];
+        } else {
+          slot = kInvalidSlot;
+          atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
+        }
+      }
+      m.buckets[hq[q]].slot = slot;
     }
   }
 }
@@ -211,6 +244,7 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
 // per CU and job streams a contiguous range of buckets.
 constexpr int kListGroups = 256;   // workgroups of the listing (all jobs together)
 constexpr uint32_t kListRun = 2048;
+constexpr int kListPer = 4;        // buckets per thread in flight
 
 __global__ __launch_bounds__(256) void list_frame_kernel(Batch b) {
   __shared__ uint32_t s_run[kListRun];
@@ -225,12 +259,11 @@ __global__ __launch_bounds__(256) void list_frame_kernel(Batch b) {
   const int lane = threadIdx.x & 63;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  for (uint32_t c0 = h0; c0 < h1; c0 += 4 * blockDim.x) {  // uniform
-    // four buckets per thread in flight
-    bool hit[4];
-    uint32_t hh[4];
+  for (uint32_t c0 = h0; c0 < h1; c0 += kListPer * blockDim.x) {  // uniform
+    bool hit[kListPer];
+    uint32_t hh[kListPer];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kListPer; ++r) {
       hh[r] = c0 + r * blockDim.x + threadIdx.x;
       hit[r] = false;
       if (hh[r] < h1) {
@@ -239,7 +272,7 @@ __global__ __launch_bounds__(256) void list_frame_kernel(Batch b) {
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kListPer; ++r) {
       const unsigned long long bal = __ballot(hit[r]);
       if (bal == 0ull) continue;  // uniform
       const int leader = __ffsll((long long)bal) - 1;
