@@ -37,7 +37,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t st, buckets, block_keys, flist, sdfw, rgb, partials, md, counts, dirty, tcache, tc_count, mesh, cells, wlist,
-      total;
+      touched, total;
   uint32_t dirty_cap, tc_tiles, cells_cap;
 };
 
@@ -65,6 +65,9 @@ Layout layout_of(const rf_map_params* p) {
   size_t o = 0;
   L.st = o; o = align256(o + sizeof(rf::DevState));
   L.buckets = o; o = align256(o + (size_t)p->num_buckets * sizeof(rf::Bucket));
+  // buckets touched by an allocation, one byte each, right after the buckets
+  // (the kernels find it there)
+  L.touched = o; o = align256(o + (size_t)p->num_buckets);
   L.block_keys = o; o = align256(o + (size_t)p->max_blocks * 8);
   L.flist = o; o = align256(o + (size_t)p->num_buckets * 4);
   const size_t rec = (p->storage == RF_STORAGE_FP32) ? 8 : 4;

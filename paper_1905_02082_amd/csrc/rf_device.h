@@ -2,7 +2,8 @@
 //
 // Map layout in the caller's HBM arena (all sections 256-byte aligned):
 //   DevState     counters and sticky flags
-//   buckets      num_buckets x 16 B  {u64 packed block key, u32 pool slot, u32 frame stamp}
+//   buckets      num_buckets x 16 B  {u64 packed block key, u32 pool slot, u32 pad}
+//   touched      num_buckets x 1 B, buckets touched by the running allocation (right after them)
 //   block_keys   max_blocks x 8 B    packed key of each pool slot
 //   flist        num_buckets x 4 B   bucket indices of the blocks the last allocation touched
 //   sdfw         max_blocks x 512 x  {f32 sdf, f32 weight} (FP32) | {f16 sdf/tau, u8 weight, pad} (FP16)
@@ -83,7 +84,7 @@ __host__ __device__ constexpr int tile_refs_before(int level) {
 struct alignas(16) Bucket {
   unsigned long long key;
   uint32_t slot;
-  uint32_t stamp;
+  uint32_t pad;  // keeps a bucket one 16-byte load
 };
 
 struct DevState {
@@ -106,8 +107,9 @@ struct DevState {
   uint32_t n_whole;        // compact free space: listed blocks carved whole by the running integration
 };
 
-// Starts a new allocation epoch: 0 is the stamp of a bucket never touched,
-// so the epoch skips it on wrap.
+// Starts a new allocation epoch (the tag of the tracking caches' entries for
+// absent blocks, which an allocation may have inserted since); 0 is skipped
+// on wrap.
 __device__ __forceinline__ void advance_epoch(DevState* st) {
   const uint32_t e = st->epoch;
   st->epoch = (e == 0xFFFFFFFFu) ? 1u : e + 1u;
@@ -149,6 +151,13 @@ struct MapDev {
   float max_weight;
   uint32_t carve_stride;
 };
+
+// Per bucket, 1 when the running allocation touched it: num_buckets bytes
+// right after the buckets in the arena (the listing that follows the
+// allocation clears what it lists).
+__host__ __device__ __forceinline__ uint8_t* touched_map(const MapDev& m) {
+  return reinterpret_cast<uint8_t*>(m.buckets + ((size_t)m.bucket_mask + 1));
+}
 
 struct FrameDev {
   const void* depth;

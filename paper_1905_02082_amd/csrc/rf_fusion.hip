@@ -3,11 +3,11 @@
 //
 // Allocation: one thread per pixel walks the block grid along its band (or
 // carve) segment with a DDA; each visited block is inserted into the hash by
-// CAS and its bucket stamped with the frame's epoch by a plain store (every
-// ray that touches it stores the same value, so no exchange is needed).
-// Carve rays run in workgroups of their own; cells are probed 12 at a time,
-// with their bucket loads and stamp stores each issued together.  A second
-// kernel then lists the buckets stamped with the epoch: the frame's block
+// CAS and its bucket marked in a byte map of touched buckets by a plain store
+// (every ray that touches it stores the same value, so no exchange is
+// needed).  Carve rays run in workgroups of their own; cells are probed 12 at
+// a time, with their bucket loads and marks each issued together.  A second
+// kernel then lists the marked buckets, clearing the marks: the frame's block
 // list, each touched block once.
 //
 // Integration: workgroups stride over the listed blocks, 256 threads x 2
@@ -24,10 +24,10 @@ namespace rf {
 
 // False when the lane just below holds the same key (and is active with a
 // valid cell): of a run of equal keys on consecutive lanes only the first
-// probes, inserts and stamps.  Neighbouring rays (consecutive pixels or
+// probes, inserts and marks.  Neighbouring rays (consecutive pixels or
 // carve-grid pixels) mostly visit the same blocks in the same order, so this
 // removes most duplicates for a few instructions; duplicates that remain are
-// harmless (the CAS insert and the stamp exchange resolve them).
+// harmless (the CAS insert resolves them, and a mark stored twice is one).
 __device__ __forceinline__ bool leads_run(unsigned long long key, bool valid, unsigned long long active) {
   const int lane = threadIdx.x & 63;
   const unsigned long long vmask = __ballot(valid) & active;
@@ -90,11 +90,12 @@ struct Dda {
   }
 };
 
-// One thread's ray: its cells' blocks are inserted if absent and stamped with
-// the frame's epoch.
+// One thread's ray: its cells' blocks are inserted if absent and their
+// buckets marked as touched.
 template <int DF>
 __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
   const MapDev& m = J.m;
+  uint8_t* touched = touched_map(m);
   const FrameDev& f = J.f;
   int u, v;
   const int s_c = (int)m.carve_stride;
@@ -112,7 +113,6 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
   }
   const uint8_t* mask = J.mask;
   const double* pose = J.pose;
-  const uint32_t frame_id = m.st->epoch;
   const int idx = v * f.W + u;
   const float D = load_depth<DF>(f, idx);
   if (!(D > 0.0f)) return;  // no measurement
@@ -177,8 +177,8 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
       k1[q] = kEmptyKey;
       if (ok[q] && bk[q].key != key[q] && bk[q].key != kEmptyKey) k1[q] = m.buckets[(hb[q] + 1u) & m.bucket_mask].key;
     }
-    // Stamp every cell's bucket with the frame (stores issued together); an
-    // absent block is inserted first
+    // Mark every cell's bucket as touched (stores issued together); an absent
+    // block is inserted first
     int hq[kBatch];
     bool claimed[kBatch];
 #pragma unroll
@@ -187,15 +187,12 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
       claimed[q] = false;
       if (!ok[q]) continue;
       int h = (int)hb[q];
-      if (bk[q].key == key[q]) {
-        if (bk[q].stamp == frame_id) continue;
-      } else if (bk[q].key != kEmptyKey && k1[q] == key[q]) {
-        h = (int)((hb[q] + 1u) & m.bucket_mask);
-      } else {
-        h = find_or_claim_from(m, cx[q], cy[q], cz[q], hb[q], bk[q].key, &claimed[q]);
+      if (bk[q].key != key[q]) {
+        if (bk[q].key != kEmptyKey && k1[q] == key[q]) h = (int)((hb[q] + 1u) & m.bucket_mask);
+        else h = find_or_claim_from(m, cx[q], cy[q], cz[q], hb[q], bk[q].key, &claimed[q]);
       }
       hq[q] = h;
-      if (h >= 0) m.buckets[h].stamp = frame_id;
+      if (h >= 0) touched[h] = 1;
     }
     // The blocks this batch inserted: key counts and pool slots (compact
     // free-space maps: none) with one counter atomic per wavefront and cell.
@@ -238,57 +235,62 @@ __global__ __launch_bounds__(256) void alloc_kernel(Batch b) {
   alloc_ray<DF>(b.job[jb], blockIdx.x - b.base[jb]);
 }
 
-// The frame's block list: every bucket stamped with the epoch, appended in
-// runs gathered per workgroup in LDS (one counter atomic per workgroup and
-// run; the order of the list is not fixed, its content is).  One workgroup
-// per CU and job streams a contiguous range of buckets.
+// The frame's block list: every bucket marked as touched, appended in runs
+// gathered per workgroup in LDS (one counter atomic per workgroup and run;
+// the order of the list is not fixed, its content is), the marks cleared on
+// the way.  One workgroup per CU and job streams a contiguous range of the
+// byte map, 16 buckets per load.
 constexpr int kListGroups = 256;   // workgroups of the listing (all jobs together)
 constexpr uint32_t kListRun = 2048;
-constexpr int kListPer = 4;        // buckets per thread in flight
 
 __global__ __launch_bounds__(256) void list_frame_kernel(Batch b) {
   __shared__ uint32_t s_run[kListRun];
   __shared__ uint32_t s_n, s_base;
   const int jb = batch_job(b, blockIdx.x);
   const MapDev& m = b.job[jb].m;
-  const uint32_t nb = m.bucket_mask + 1u;
-  const uint32_t epoch = m.st->epoch;
+  const uint32_t nc = (m.bucket_mask + 16u) / 16u;  // 16-byte chunks of the map
   const uint32_t g0 = blockIdx.x - b.base[jb], gn = b.base[jb + 1] - b.base[jb];
-  const uint32_t per = (nb + gn - 1) / gn;
-  const uint32_t h0 = g0 * per, h1 = min(h0 + per, nb);
-  const int lane = threadIdx.x & 63;
+  const uint32_t per = (nc + gn - 1) / gn;
+  const uint32_t c0 = g0 * per, c1 = min(c0 + per, nc);
+  uint4* map = reinterpret_cast<uint4*>(touched_map(m));
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  for (uint32_t c0 = h0; c0 < h1; c0 += kListPer * blockDim.x) {  // uniform
-    bool hit[kListPer];
-    uint32_t hh[kListPer];
+  for (uint32_t cb = c0; cb < c1; cb += blockDim.x) {  // uniform
+    const uint32_t c = cb + threadIdx.x;
+    const uint4 w = c < c1 ? map[c] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    uint32_t cnt = 0;
 #pragma unroll
-    for (int r = 0; r < kListPer; ++r) {
-      hh[r] = c0 + r * blockDim.x + threadIdx.x;
-      hit[r] = false;
-      if (hh[r] < h1) {
-        const Bucket bk = m.buckets[hh[r]];
-        hit[r] = bk.key != kEmptyKey && bk.stamp == epoch;
-      }
+    for (int k = 0; k < 4; ++k) cnt += __popc(words[k] & 0x01010101u);
+    if (cnt) map[c] = make_uint4(0u, 0u, 0u, 0u);
+    // positions in the workgroup's run: a prefix over the wavefront's counts
+    // (shuffles), one LDS atomic per wavefront
+    uint32_t pre = cnt;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(pre, o);
+      if (lane >= o) pre += t;
     }
+    const uint32_t total = __shfl(pre, 63);
+    uint32_t base = 0;
+    if (total && lane == 63) base = atomicAdd(&s_n, total);  // LDS
+    base = __shfl(base, 63);
+    uint32_t i = base + pre - cnt;
 #pragma unroll
-    for (int r = 0; r < kListPer; ++r) {
-      const unsigned long long bal = __ballot(hit[r]);
-      if (bal == 0ull) continue;  // uniform
-      const int leader = __ffsll((long long)bal) - 1;
-      uint32_t pos = 0;
-      if (lane == leader) pos = atomicAdd(&s_n, (uint32_t)__popcll(bal));  // LDS
-      pos = __shfl(pos, leader);
-      const uint32_t i = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      if (hit[r]) {
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int by = 0; by < 4; ++by) {
+        if (!((words[k] >> (8 * by)) & 1u)) continue;
+        const uint32_t h = c * 16u + 4u * k + by;
         if (i < kListRun) {
-          s_run[i] = hh[r];
+          s_run[i] = h;
         } else {
           // past the run's capacity: straight to the frame list
-          const uint32_t k = atomicAdd(&m.st->f_count, 1u);
-          if (k < m.flist_cap) m.flist[k] = hh[r];
+          const uint32_t kk = atomicAdd(&m.st->f_count, 1u);
+          if (kk < m.flist_cap) m.flist[kk] = h;
         }
+        ++i;
       }
     }
   }
@@ -302,9 +304,9 @@ __global__ __launch_bounds__(256) void list_frame_kernel(Batch b) {
   }
 }
 
-// Starts an allocation: empties the frame list and advances the epoch that
-// stamps the buckets this frame touches.  The epoch lives on the device, so a
-// recorded launch sequence (a HIP graph of a frame) replays correctly.
+// Starts an allocation: empties the frame list and advances the allocation
+// epoch.  Both live on the device, so a recorded launch sequence (a HIP graph
+// of a frame) replays correctly.
 __global__ void reset_frame_list_kernel(Batch b) {
   if (threadIdx.x == 0 && (int)blockIdx.x < b.n) {
     DevState* st = b.job[blockIdx.x].m.st;

@@ -10,7 +10,7 @@ __global__ void init_buckets_kernel(Bucket* b, uint32_t n) {
     Bucket e;
     e.key = kEmptyKey;
     e.slot = kInvalidSlot;
-    e.stamp = 0;
+    e.pad = 0;
     b[i] = e;
   }
 }
@@ -59,6 +59,8 @@ void launch_map_init(const MapDev& m, uint32_t num_buckets, int storage, hipStre
   init_refs_kernel<<<256, 256, 0, s>>>(m.tcache, (size_t)tile_refs_before(kCacheLevels) * m.tc_tiles);
   zero_words_kernel<<<16, 256, 0, s>>>(reinterpret_cast<uint4*>(m.tc_count), ((size_t)kCacheLevels * m.tc_tiles + 3) / 4);
   init_buckets_kernel<<<2048, 256, 0, s>>>(m.buckets, num_buckets);
+  // no bucket touched; every listing leaves the map so
+  zero_words_kernel<<<256, 256, 0, s>>>(reinterpret_cast<uint4*>(touched_map(m)), ((size_t)num_buckets + 15) / 16);
   // the flood-fill tile flags start at zero, and every mask computation
   // leaves them so
   zero_words_kernel<<<16, 256, 0, s>>>(reinterpret_cast<uint4*>(m.dirty), ((size_t)m.dirty_cap * 2 * 4 + 15) / 16);

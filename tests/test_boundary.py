@@ -79,7 +79,7 @@ def test_hashmap_bytes_layout(N):
     nb, mb = 1 << 20, 1 << 17
     tcache = (64 + 128 + 512 + 512) * ((640 * 480 + 255) // 256 + 64) * 16   # tracking block cache: pairs per tile at levels 0-3
     tcache += 4 * ((640 * 480 + 255) // 256 + 64) * 4                 # and their counts
-    core = nb * 16 + mb * 8 + nb * 4 + mb * 512 * 8 + mb * 512 * 4 + tcache
+    core = nb * 16 + nb + mb * 8 + nb * 4 + mb * 512 * 8 + mb * 512 * 4 + tcache   # buckets + touched-bucket map
     assert core <= n.value <= core + 256 * 16 + 512 * 32 * 8 + 640 * 480 * 2
     p16 = params(N, storage=1)
     n16 = ctypes.c_size_t(0)
