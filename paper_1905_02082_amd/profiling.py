@@ -84,6 +84,29 @@ def summary(path, kernel=None, by_grid=False, out=sys.stdout):
               file=out)
 
 
+def last_frames(path, n, out=sys.stdout):
+    """Per-kernel time over the last n frames of a kernel trace (a frame ends
+    with the integration's fold launch), and the idle time between one
+    kernel's end and the next one's start."""
+    c = _db(path)
+    rows = list(c.execute("select name, start, duration from kernels order by start"))
+    ends = [i for i, r in enumerate(rows) if "integ_fold_kernel" in r[0]]
+    if len(ends) < n + 1:
+        raise SystemExit("fewer than %d frames in the trace" % (n + 1))
+    sel = rows[ends[-n - 1] + 1:ends[-1] + 1]
+    by = {}
+    for name, _, d in sel:
+        by.setdefault(re.sub(r"\(.*", "", name), []).append(d / 1e3)
+    span = (sel[-1][1] + sel[-1][2] - sel[0][1]) / 1e3
+    busy = sum(r[2] for r in sel) / 1e3
+    print("last %d frames: %d dispatches, %.1f us per frame, kernel time %.1f us per frame, idle %.1f us per "
+          "frame (%.2f us per dispatch)" % (n, len(sel), span / n, busy / n, (span - busy) / n, (span - busy) / len(sel)),
+          file=out)
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        print("  %-60s n %5d  avg %8.2f us  per frame %8.1f us" % (k[:60], len(v), sum(v) / len(v), sum(v) / n),
+              file=out)
+
+
 def _counter(path, counter, kernel):
     """Per-dispatch values (dispatch order) of one counter for kernels matching the regex."""
     c = _db(path)
@@ -143,6 +166,9 @@ def main():
     s.add_argument("dir")
     s.add_argument("--kernel", default=None)
     s.add_argument("--by-grid", action="store_true")
+    f = sub.add_parser("frames")
+    f.add_argument("dir")
+    f.add_argument("--last", type=int, default=20)
     p = sub.add_parser("pmc")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -159,6 +185,8 @@ def main():
         copy_kernel(args.mib, args.reps)
     elif args.cmd == "summary":
         summary(args.dir, args.kernel, args.by_grid)
+    elif args.cmd == "frames":
+        last_frames(args.dir, args.last)
     else:
         pmc(args)
 
