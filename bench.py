@@ -26,10 +26,12 @@ from device counters of voxel updates.  Extra measurements after the
 headline: the same sequence in FP16+u8 storage ("fp16", with its final pose
 against FP32's), with compact free space ("compact": blocks carved whole,
 free blocks without voxels; its final pose against the per-voxel map's and
-its voxel memory), with the clipping plane at 5 m ("depth_max_5m"), and the
-640x480 static room of 300 frames at 1 cm voxels ("static_room").  The CPU
-oracle is timed on a bounded sample of the headline sequence, single-thread
-and with all host cores ("cpu_baseline").
+its voxel memory), with the clipping plane at 5 m ("depth_max_5m"), the
+640x480 static room of 300 frames at 1 cm voxels ("static_room"), and the
+640x480 dynamic room of 400 frames with moving clusters ("dynamic_room", with
+the dynamic mask's IoU against the generator's mover labels).  The CPU oracle
+is timed on a bounded sample of the headline sequence, single-thread and with
+all host cores, per stage too ("cpu_baseline").
 """
 from __future__ import annotations
 
@@ -231,19 +233,21 @@ def cpu_baseline(seq, budget_s=30.0, threads=1):
     fr = O.Frame(seq.depth[0], seq.rgb[0], *seq.intrinsics, depth_scale=seq.depth_scale)
     T, _ = O.process_frame(a, fr, T, 0, seq.levels, seq.iters, mask_map=b)
     done, spent = 0, 0.0
+    times = {}
     k = 1
     while k < seq.n and (done == 0 or spent < budget_s):
         fr = O.Frame(seq.depth[k], seq.rgb[k], *seq.intrinsics, depth_scale=seq.depth_scale)
         t0 = time.perf_counter()
-        T, _ = O.process_frame(a, fr, T, k, seq.levels, seq.iters, mask_map=b)
+        T, _ = O.process_frame(a, fr, T, k, seq.levels, seq.iters, mask_map=b, times=times)
         spent += time.perf_counter() - t0
         done += 1
         k += 1
         log("cpu oracle (%d threads) frame %d: %.2f s" % (threads, k - 1, spent / done))
     used = lib.orc_get_threads() if threads > 1 else 1
+    stages = {k2: round(1000.0 * v / done, 2) for k2, v in times.items()}
     return done / spent, ("frames 1-%d of the headline sequence (full method per frame after frame-0 fusion), "
                           "FP64 oracle + FP32 mask mirror, %s" % (done, "%d OpenMP threads" % used if threads > 1
-                                                                  else "single thread")), used
+                                                                  else "single thread")), used, stages
 
 
 def host_cpu():
@@ -289,6 +293,43 @@ def h2d_measurement(seq, frames, ks, dev):
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     return float(np.median(ms)), int(dh.numel() * dh.element_size() + ch.numel())
+
+
+def mask_iou_measurement(seq, frames, dev, first=10):
+    """Quality of the dynamic mask against the generator's labels (pixels
+    whose first hit is a mover): the method runs over the whole sequence
+    (untimed, FP32), and from frame `first` on each frame's final mask is
+    compared pixel by pixel with the labels.  Reports the IoU of the frames
+    with movers in view (mean, median) and over all their pixels."""
+    import numpy as np
+    import torch
+
+    import paper_1905_02082_amd as rf
+    mp = rf.MapParams(seq.voxel_size, seq.truncation, seq.depth_max, seq.num_buckets, WORKLOAD_BLOCKS[seq.name], 255,
+                      seq.carve_stride, "fp32", seq.width * seq.height)
+    tp = rf.TrackParams(seq.levels, seq.iters, 0.025, 64, 0.0)
+    mk = rf.MaskParams(0.5, 0.007)
+    s = rf.Session(mp, seq.poses[0], dev)
+    inter, union = [], []
+    for k in range(seq.n):
+        rf.process_batch([s], [frames[k]], tp, mk, True)
+        if k < first:
+            continue
+        gt = torch.from_numpy(seq.labels[k] > 0).to(dev)
+        m = s.mask > 0
+        inter.append(torch.logical_and(m, gt).sum())
+        union.append(torch.logical_or(m, gt).sum())
+    torch.cuda.synchronize()
+    inter = np.array([int(x) for x in inter], np.int64)
+    union = np.array([int(x) for x in union], np.int64)
+    movers = union > 0
+    iou = inter[movers] / union[movers]
+    del s
+    return {"frames": int(len(inter)), "frames_with_movers": int(movers.sum()),
+            "mean_iou": round(float(iou.mean()), 4) if len(iou) else None,
+            "median_iou": round(float(np.median(iou)), 4) if len(iou) else None,
+            "pixel_iou": round(float(inter.sum() / max(union.sum(), 1)), 4),
+            "note": "final mask of every frame from frame %d on against the pixels whose first hit is a mover" % first}
 
 
 def run_workload(seq, frames, storage, W, K, B, dev, name, depth_max=None, free_blocks=False):
@@ -479,7 +520,7 @@ def main():
     ap.add_argument("--storage", default=None, choices=["fp32", "fp16"],
                     help="voxel storage (default fp32; serving default fp16)")
     ap.add_argument("--depth-max", type=float, default=None, help="clipping plane (default: the workload's)")
-    ap.add_argument("--extras", default="fp16,compact,depth_max_5m,static_room",
+    ap.add_argument("--extras", default="fp16,compact,depth_max_5m,static_room,dynamic_room",
                     help="comma list of extra measurements after the headline: fp16 (same sequence, FP16+u8 "
                          "storage), compact (same sequence, compact free space), depth_max_5m (same sequence, "
                          "clipping plane 5 m), static_room (300 frames), or none")
@@ -523,7 +564,7 @@ def main():
     if not 1 <= B <= 8:
         raise SystemExit("--batch must be in [1, 8]")
     extras = [] if args.extras in ("", "none") else args.extras.split(",")
-    order = ("fp16", "compact", "depth_max_5m", "static_room")  # static_room last: it replaces the frames
+    order = ("fp16", "compact", "depth_max_5m", "static_room", "dynamic_room")  # the rooms last: they replace the frames
     for e in extras:
         if e not in order:
             raise SystemExit("unknown extra %s" % e)
@@ -588,32 +629,38 @@ def main():
             elif e == "depth_max_5m" and (args.depth_max or seq.depth_max) != 5.0:
                 r, ss = run_workload(seq, frames, storage, W, K, 1, dev, "depth_max_5m", 5.0)
                 out["depth_max_5m"] = r
-            elif e == "static_room" and args.workload != "static_room":
-                del frames
+            elif e in ("static_room", "dynamic_room") and args.workload != e:
+                if frames is not None:
+                    del frames
+                    frames = None
                 torch.cuda.empty_cache()
-                sq = make_sequence("static_room", WORKLOAD_FRAMES["static_room"])
+                sq = make_sequence(e, WORKLOAD_FRAMES[e])
                 fr2 = upload_frames(sq, dev)
-                r, ss = run_workload(sq, fr2, "fp32", W, K, 1, dev, "static_room")
+                r, ss = run_workload(sq, fr2, "fp32", W, K, 1, dev, e)
                 r["workload"] = workload_text(sq, r)
-                out["static_room"] = r
+                if e == "dynamic_room":
+                    del ss
+                    ss = []
+                    torch.cuda.empty_cache()
+                    r["mask_iou"] = mask_iou_measurement(sq, fr2, dev)
+                    log("dynamic_room: mask IoU %s" % r["mask_iou"]["mean_iou"])
+                out[e] = r
                 del fr2
-                frames = None
             else:
                 continue
             del ss
             torch.cuda.empty_cache()
-            if frames is None:
-                break
     if not args.no_cpu_baseline and B == 1:
         ncpu, model = host_cpu()
         # all the host cores this process may use: the affinity set, capped by
         # OMP_NUM_THREADS where the host assigns a share of its cores
         share = int(os.environ.get("OMP_NUM_THREADS") or ncpu)
-        v1, sample1, _ = cpu_baseline(seq, args.cpu_budget, threads=1)
-        vn, samplen, used = cpu_baseline(seq, args.cpu_budget, threads=max(2, min(ncpu, share)))
+        v1, sample1, _, st1 = cpu_baseline(seq, args.cpu_budget, threads=1)
+        vn, samplen, used, stn = cpu_baseline(seq, args.cpu_budget, threads=max(2, min(ncpu, share)))
         out["cpu_baseline"] = {"value": round(vn, 5), "unit": "frames/s", "cores": used, "kind": "oracle",
-                               "sample": samplen, "cpu_model": model, "nproc": ncpu,
-                               "single_thread": {"value": round(v1, 5), "cores": 1, "sample": sample1}}
+                               "sample": samplen, "cpu_model": model, "nproc": ncpu, "stages_ms": stn,
+                               "single_thread": {"value": round(v1, 5), "cores": 1, "sample": sample1,
+                                                 "stages_ms": st1}}
     print(json.dumps(out), flush=True)
     # release every map (and its arena) and drain the stream before the
     # interpreter shuts down, so no destructor runs against a torn-down runtime

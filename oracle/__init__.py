@@ -343,11 +343,22 @@ def morph3x3(mask, erode):
 
 
 def process_frame(omap: OracleMap, fr: Frame, pose_prev, k, levels, iters, w_c=0.025, gamma=0.5,
-                  theta=0.007, min_valid=64, dynamic=True, mask_map: OracleMap | None = None):
+                  theta=0.007, min_valid=64, dynamic=True, mask_map: OracleMap | None = None,
+                  times: dict | None = None):
     """One frame of the method (Fig. 2 order): initial registration, residual
     mask, registration without masked pixels, allocation, integration.  Frame 0
     only allocates and integrates at ``pose_prev``.  ``mask_map`` (FP32 mirror
-    holding the same map) supplies the FP32 mask decision when omap is FP64."""
+    holding the same map) supplies the FP32 mask decision when omap is FP64.
+    ``times`` (optional) accumulates the seconds of each stage (track1, mask,
+    track2, allocate, integrate, and mirror: the FP32 mirror's fusion)."""
+    import time
+    clock = [time.perf_counter()]
+
+    def lap(stage):
+        if times is not None:
+            t = time.perf_counter()
+            times[stage] = times.get(stage, 0.0) + t - clock[0]
+            clock[0] = t
     if k == 0:
         omap.allocate(fr, pose_prev)
         omap.integrate(fr, pose_prev)
@@ -356,15 +367,21 @@ def process_frame(omap: OracleMap, fr: Frame, pose_prev, k, levels, iters, w_c=0
             mask_map.integrate(fr, pose_prev)
         return np.array(pose_prev), None
     T1, _, _ = omap.track(fr, pose_prev, levels, iters, w_c, min_valid)
+    lap("track1")
     mask = None
     T = T1
     if dynamic:
         mm = mask_map if mask_map is not None else omap
         mask = mm.mask(fr, T1, gamma, theta)["final"]
+        lap("mask")
         T, _, _ = omap.track(fr, T1, levels, iters, w_c, min_valid, mask=mask)
+        lap("track2")
     omap.allocate(fr, T, mask)
+    lap("allocate")
     omap.integrate(fr, T, mask)
+    lap("integrate")
     if mask_map is not None and mask_map is not omap:
         mask_map.allocate(fr, T, mask)
         mask_map.integrate(fr, T, mask)
+        lap("mirror")
     return T, mask
