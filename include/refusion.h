@@ -70,7 +70,7 @@ typedef int32_t rf_status;
 
 typedef struct {
   float fx, fy, cx, cy;   /* pinhole intrinsics (Eq. 1) */
-  int32_t width, height;  /* pixels */
+  int32_t width, height;  /* pixels; width*height <= 2^26 and ceil(width/16)*ceil(height/16) <= 2^18 */
   const void* depth;      /* device, height*width of uint16 or float32 */
   int32_t depth_format;   /* RF_DEPTH_U16 | RF_DEPTH_F32 */
   float depth_scale;      /* metres per uint16 unit (e.g. 0.001); ignored for float32 */

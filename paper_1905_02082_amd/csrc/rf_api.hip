@@ -96,7 +96,8 @@ Layout layout_of(const rf_map_params* p) {
 
 rf_status make_frame(const rf_frame* f, rf::FrameDev& out) {
   if (!f) return fail(RF_EINVAL, "frame is NULL");
-  if (f->width <= 0 || f->height <= 0 || (int64_t)f->width * f->height > (1 << 26))
+  if (f->width <= 0 || f->height <= 0 || (int64_t)f->width * f->height > (1 << 26) ||
+      (int64_t)((f->width + 15) / 16) * ((f->height + 15) / 16) > (1 << 18))  // tracking tiles (fixed-point range)
     return fail(RF_EINVAL, "bad frame size %dx%d", f->width, f->height);
   if (!f->depth || !f->rgb) return fail(RF_EINVAL, "frame depth/rgb is NULL");
   if (f->depth_format != RF_DEPTH_U16 && f->depth_format != RF_DEPTH_F32) return fail(RF_EINVAL, "bad depth_format");

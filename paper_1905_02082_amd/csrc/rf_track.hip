@@ -8,11 +8,12 @@
 // FP32 factors are exact in FP64) with a fixed-order transposed reduction
 // over its pixels, and adds them to device-wide accumulators.
 //
-// The accumulators are 96-bit fixed point (units of 2^-60) held as three
-// 32-bit chunks in 64-bit words and summed with device-scope integer atomics:
-// integer addition is associative, so the totals do not depend on the order
-// in which workgroups finish (bit-reproducible), and the chunks need no carry
-// chain, so every atomic is independent.  Workgroups spread over kAccCopies
+// The accumulators are fixed point (units of 2^-60) held as two chunks in
+// 64-bit words, the low 48 bits and the signed rest, and summed with
+// device-scope integer atomics: integer addition is associative, so the
+// totals do not depend on the order in which workgroups finish
+// (bit-reproducible), and the chunks need no carry chain, so every atomic is
+// independent (the low chunk's sums keep 16 bits of headroom for carries).  Workgroups spread over kAccCopies
 // copies of the accumulators (fewer atomics per address), which the reader
 // sums exactly.  Nothing in a launch waits for the
 // other workgroups: the solve of iteration j runs at the start of launch j+1,
@@ -55,10 +56,10 @@ struct TrackArgs {
 __device__ __forceinline__ unsigned long long* acc_buf(const MapDev& m, int b) {
   return reinterpret_cast<unsigned long long*>(m.partials) + (size_t)b * kBufWords;
 }
-// The words an accumulator buffer actually uses: three chunks and a range
+// The words an accumulator buffer actually uses: two chunks and a range
 // marker per term per copy (the rest of each 128-byte line is padding against
-// false sharing).
-constexpr int kUsedPerTerm = 4;
+// false sharing: atomics on one line are served one after another).
+constexpr int kUsedPerTerm = 3;
 constexpr int kUsedWords = kAccCopies * kNE * kUsedPerTerm;
 __device__ __forceinline__ unsigned long long* used_word(unsigned long long* buf, int q) {
   const int copy = q / (kNE * kUsedPerTerm), r = q % (kNE * kUsedPerTerm);
@@ -74,47 +75,51 @@ __device__ __forceinline__ double* lm_state(const MapDev& m, int b) {
   return reinterpret_cast<double*>(m.partials) + (size_t)3 * kBufWords + 32 + kLmWords * b;
 }
 
-// Adds v to a term: v 2^60 truncated toward zero as a 96-bit two's
-// complement integer c0 + c1 2^32 + c2 2^64 (c0, c1 unsigned 32-bit, c2 signed).
-// A non-finite v, or |v| >= 2^34 (beyond the range the totals can hold), is
-// not added: the term's range marker acc[3] is set instead, and its total
-// then reads as NaN, which stops the registration pass (RF_FLAG_TRACK_RANGE).
-// Returns false in that case.
+// Adds v to a term: v 2^60 truncated toward zero as a two's complement
+// integer lo + hi 2^48 (lo unsigned 48-bit, hi signed 64-bit), two atomics
+// (one where hi is 0).  The low chunks of a copy sum below 2^63 for up to 2^15
+// workgroups (a 2^26-pixel frame's tiles over the copies), the high chunks of
+// terms below 2^34 likewise.  A non-finite v, or |v| >= 2^34 (beyond that
+// range), is not added: the term's range marker acc[2] is set instead, and
+// its total then reads as NaN, which stops the registration pass
+// (RF_FLAG_TRACK_RANGE).  Returns false in that case.
 __device__ __forceinline__ bool fixed_add(unsigned long long* acc, double v) {
   double a = fabs(v) * kFixScale;
   if (!(a < 0x1p94)) {
-    atomicOr(&acc[3], 1ull);
+    atomicOr(&acc[2], 1ull);
     return false;
   }
-  const double hi_d = floor(a * 0x1p-64);
+  const double hi_d = floor(a * 0x1p-48);
   unsigned long long hi = (unsigned long long)hi_d;
-  unsigned long long lo = (unsigned long long)(a - hi_d * 0x1p64);
+  unsigned long long lo = (unsigned long long)(a - hi_d * 0x1p48);
   if (v < 0.0) {
-    lo = ~lo + 1ull;
     hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+    lo = (0ull - lo) & 0xFFFFFFFFFFFFull;
   }
-  const unsigned long long c0 = lo & 0xFFFFFFFFull, c1 = lo >> 32, c2 = hi;
-  if (c0) atomicAdd(&acc[0], c0);
-  if (c1) atomicAdd(&acc[1], c1);
-  if (c2) atomicAdd(&acc[2], c2);
+  if (lo) atomicAdd(&acc[0], lo);
+  if (hi) atomicAdd(&acc[1], hi);
   return true;
 }
 
-// Total of a term over the accumulator copies as FP64 (exact integer sums and
-// 128-bit combination, one final rounding).
-// A term whose range marker is set in any copy totals NaN.
+// Total of a term over the accumulator copies as FP64 (exact 128-bit integer
+// sum, then conversion).  A term whose range marker is set in any copy
+// totals NaN.
 __device__ __forceinline__ double fixed_total(const unsigned long long* acc) {
-  unsigned long long s0 = 0, s1 = 0, s2 = 0, bad = 0;
+  unsigned long long lo = 0, hi = 0, bad = 0;
 #pragma unroll
   for (int c = 0; c < kAccCopies; ++c) {
-    s0 += acc[c * kCopyWords];
-    s1 += acc[c * kCopyWords + 1];
-    s2 += acc[c * kCopyWords + 2];
-    bad |= acc[c * kCopyWords + 3];
+    const unsigned long long s0 = acc[c * kCopyWords];
+    const long long s1 = (long long)acc[c * kCopyWords + 1];
+    bad |= acc[c * kCopyWords + 2];
+    // s1 2^48 + s0 as a 128-bit two's complement number, added to (hi, lo)
+    const unsigned long long l1 = (unsigned long long)s1 << 48;
+    const unsigned long long h1 = (unsigned long long)(s1 >> 16);
+    const unsigned long long n = lo + l1;
+    hi += h1 + (n < lo ? 1ull : 0ull);
+    lo = n + s0;
+    hi += (lo < n ? 1ull : 0ull);
   }
   if (bad) return __longlong_as_double(0x7FF8000000000000ll);
-  unsigned long long lo = s0 + (s1 << 32);
-  unsigned long long hi = s2 + (s1 >> 32) + (lo < s0 ? 1ull : 0ull);
   const bool neg = (long long)hi < 0;
   if (neg) {
     lo = ~lo + 1ull;

@@ -133,6 +133,19 @@ def test_raycast_and_mesh_argument_checks(N):
     assert L.extract_mesh(fake, None, 10, ctypes.c_void_p(0x6000), None) == N.RF_EINVAL
 
 
+def test_frame_shape_checks(N):
+    """Frames beyond 2^26 pixels, or beyond 2^18 tracking tiles of 16x16
+    (the range the fixed-point normal-equation totals are sized for), are
+    rejected on the host before the map is used (dummy pointers again)."""
+    L = N.load()
+    fake = ctypes.c_void_p(0x1000)
+    pose, out = ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000)
+    for w, h in [(0, 60), (80, -1), (1 << 14, 1 << 13), (1, 1 << 23), (17, (1 << 26) // 17)]:
+        fr = N.RfFrame(100.0, 100.0, 40.0, 30.0, w, h, 0x2000, N.RF_DEPTH_F32, 1.0, 0x3000)
+        assert L.raycast_depth(fake, ctypes.byref(fr), pose, 0.3, 5.0, 5.0, 1, out, None) == N.RF_EINVAL, (w, h)
+        assert "frame size" in L.rf_last_error().decode()
+
+
 def test_package_has_no_cpu_fallback():
     """The product package must not import the oracle."""
     pkg = os.path.join(ROOT, "paper_1905_02082_amd")
