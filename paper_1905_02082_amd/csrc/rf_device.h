@@ -250,13 +250,15 @@ __device__ __forceinline__ int find_or_insert_from(const MapDev& m, int x, int y
 // As find_or_insert_from, but a block this call inserts gets no pool slot
 // and is not counted here (*claimed is set): the caller assigns slots and
 // counts for a whole wavefront at once (one counter atomic instead of one
-// per new block).
-__device__ __forceinline__ int find_or_claim_from(const MapDev& m, int x, int y, int z, uint32_t h,
+// per new block).  The probe starts i0 buckets past the home bucket `home`,
+// whose key k the caller has already read.
+__device__ __forceinline__ int find_or_claim_from(const MapDev& m, int x, int y, int z, uint32_t home, uint32_t i0,
                                                   unsigned long long k, bool* claimed) {
   const unsigned long long key = pack_key(x, y, z);
   *claimed = false;
-  for (uint32_t i = 0; i < m.max_probe; ++i) {
-    if (i > 0) k = m.buckets[h].key;
+  uint32_t h = (home + i0) & m.bucket_mask;
+  for (uint32_t i = i0; i < m.max_probe; ++i) {
+    if (i > i0) k = m.buckets[h].key;
     if (k == key) return (int)h;
     if (k == kEmptyKey) {
       const unsigned long long old = atomicCAS(&m.buckets[h].key, kEmptyKey, key);

@@ -156,9 +156,8 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
         if (d.left > 0) d.advance();
       }
     }
-    unsigned long long key[kBatch];
+    unsigned long long key[kBatch], bkey[kBatch];
     uint32_t hb[kBatch];
-    Bucket bk[kBatch];
     const unsigned long long active = __ballot(true);
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
@@ -166,16 +165,19 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
       ok[q] = leads_run(key[q], ok[q], active);
       if (!ok[q]) continue;
       hb[q] = hash3(cx[q], cy[q], cz[q]) & m.bucket_mask;
-      bk[q] = m.buckets[hb[q]];
+      bkey[q] = m.buckets[hb[q]].key;
     }
-    // Cells whose home bucket holds another block: the next bucket's key,
-    // loaded for all of them together (linear probing puts most displaced
-    // blocks there), before any probes on.
-    unsigned long long k1[kBatch];
+    // Cells whose home bucket holds another block: the keys of the next
+    // two buckets, loaded for all of them together (linear probing puts
+    // most displaced blocks there), before any probes on.
+    unsigned long long k1[kBatch], k2[kBatch];
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
-      k1[q] = kEmptyKey;
-      if (ok[q] && bk[q].key != key[q] && bk[q].key != kEmptyKey) k1[q] = m.buckets[(hb[q] + 1u) & m.bucket_mask].key;
+      k1[q] = k2[q] = kEmptyKey;
+      if (ok[q] && bkey[q] != key[q] && bkey[q] != kEmptyKey) {
+        k1[q] = m.buckets[(hb[q] + 1u) & m.bucket_mask].key;
+        k2[q] = m.buckets[(hb[q] + 2u) & m.bucket_mask].key;
+      }
     }
     // Mark every cell's bucket as touched (stores issued together); an absent
     // block is inserted first
@@ -187,9 +189,17 @@ __device__ __forceinline__ void alloc_ray(const Job& J, int g) {
       claimed[q] = false;
       if (!ok[q]) continue;
       int h = (int)hb[q];
-      if (bk[q].key != key[q]) {
-        if (bk[q].key != kEmptyKey && k1[q] == key[q]) h = (int)((hb[q] + 1u) & m.bucket_mask);
-        else h = find_or_claim_from(m, cx[q], cy[q], cz[q], hb[q], bk[q].key, &claimed[q]);
+      if (bkey[q] == kEmptyKey) {
+        h = find_or_claim_from(m, cx[q], cy[q], cz[q], hb[q], 0u, kEmptyKey, &claimed[q]);
+      } else if (bkey[q] != key[q]) {
+        if (k1[q] == key[q]) h = (int)((hb[q] + 1u) & m.bucket_mask);
+        else if (k2[q] == key[q]) h = (int)((hb[q] + 2u) & m.bucket_mask);
+        else {
+          // absent (insert at the first empty bucket) or further on
+          const uint32_t i0 = (k1[q] == kEmptyKey) ? 1u : 2u;
+          const unsigned long long k0 = (i0 == 1u) ? k1[q] : k2[q];
+          h = find_or_claim_from(m, cx[q], cy[q], cz[q], hb[q], i0, k0, &claimed[q]);
+        }
       }
       hq[q] = h;
       if (h >= 0) touched[h] = 1;

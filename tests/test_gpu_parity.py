@@ -511,6 +511,35 @@ def test_full_size_large_rooms_allocation(rf):
     assert flags == 0 and nb == o32.num_blocks
 
 
+def test_frame_list_beyond_a_listing_run(rf):
+    """Eight maps allocated in one batch (the listing then gives each map 32
+    workgroups, each streaming a 32nd of its buckets) on a 640x480 frame
+    facing a wall at 2.5 m with 0.5 cm voxels: about 100 k blocks, more than
+    32 x 2048, so at least one workgroup's range holds more marked buckets
+    than its 2048-entry run in LDS and appends the rest to the frame list one
+    atomic each.  Every map's frame list equals the oracle's block set."""
+    from paper_1905_02082_amd import _native as N
+    W, H = 640, 480
+    intr = (525.0, 525.0, 319.5, 239.5)
+    depth = np.full((H, W), 2500, np.uint16)
+    rgb = np.random.default_rng(11).integers(0, 256, (H, W, 3), dtype=np.uint8)
+    T = np.eye(4)
+    T[:3, 3] = [0.013, -0.021, 0.007]
+    o32 = O.OracleMap(0.005, 0.03, 3.5, 255, 2, real_bits=32)
+    F_orc = o32.allocate(O.Frame(depth, rgb, *intr, depth_scale=0.001), T)
+    assert len(F_orc) > 32 * 2048
+    params = rf.MapParams(0.005, 0.03, 3.5, 1 << 18, 1 << 17, 255, 2, "fp32", W * H)
+    sessions = [rf.Session(params, T) for _ in range(8)]
+    frames = [rf.Frame.from_numpy(depth, rgb, *intr, depth_scale=0.001)] * 8
+    L = N.load()
+    assert L.hashmap_allocate_batch(rf._jobs(sessions, frames), 8, None) == 0
+    torch.cuda.synchronize()
+    for s in sessions:
+        assert np.array_equal(gpu_keyset(s.map.frame_blocks()), F_orc)
+        flags, nb = s.map.status()
+        assert flags == 0 and nb == len(F_orc)
+
+
 def test_track_is_deterministic(rf, room):
     """Order-independent fixed-point reduction: repeated runs are bit-identical."""
     m, _, _ = integrate_teacher_forced(rf, room, range(2))
