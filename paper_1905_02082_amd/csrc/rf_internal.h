@@ -67,6 +67,8 @@ void launch_track(Batch& b, int depth_format, int storage, const rf_track_params
 void launch_normal_equations(Batch& b, int depth_format, int storage, int level, float w_c, double* out29,
                              hipStream_t s);
 void launch_mask(Batch& b, int depth_format, int storage, const rf_mask_params& mp, hipStream_t s);
+// residual and raw decision of the mask (its first stage), through the tracking tile cache
+void launch_residual(Batch& b, int depth_format, int storage, float gamma, hipStream_t s);
 
 void launch_map_init(const MapDev& m, uint32_t num_buckets, int storage, hipStream_t s);
 void launch_surface(const MapDev& m, int storage, float* pts, uint32_t cap, uint32_t* count, hipStream_t s);

@@ -1,6 +1,8 @@
 // Residual-based dynamics mask (Sec. III-C, Algorithm 1) for gfx950.
 //
 //   residual_kernel   r = S(T x)^2 per valid pixel, raw = r > gamma tau^2
+//                     (with the tracking kernels: its corner blocks resolve
+//                     through the tracking tile cache)
 //   pixel_pass 0      3x3 erosion (outside the image counts as 0) -> seeds
 //   flood_tiles       every 32x32 tile (plus 1-pixel halo) in LDS grows the
 //                     seeds to its local fixpoint; a tile whose new border
@@ -22,35 +24,6 @@
 #include "rf_internal.h"
 
 namespace rf {
-
-template <int DF, int STORAGE>
-__global__ __launch_bounds__(256) void residual_kernel(Batch b, float gamma) {
-  const int jb = batch_job(b, blockIdx.x);
-  const Job& J = b.job[jb];
-  const MapDev& m = J.m;
-  const FrameDev& f = J.f;
-  const int idx = (blockIdx.x - b.base[jb]) * blockDim.x + threadIdx.x;
-  if (idx >= f.W * f.H) return;
-  const int u = idx % f.W, v = idx / f.W;
-  const float D = load_depth<DF>(f, idx);
-  const float thr = gamma * (m.tau * m.tau);
-  uint8_t out = 0;
-  float r = -1.0f;
-  if (depth_ok(D, m.dmax)) {
-    float R[9], t[3];
-    load_pose_f(J.pose, R, t);
-    const float x[3] = {(((float)u - f.cx) * f.ifx) * D, (((float)v - f.cy) * f.ify) * D, D};
-    float y[3];
-    xform(R, t, x, y);
-    float S, Iv, g3[3], h3[3];
-    if (sample_map<STORAGE, false, false>(m, y, S, g3, Iv, h3)) {
-      r = S * S;
-      out = (r > thr) ? 1 : 0;
-    }
-  }
-  (J.raw ? J.raw : J.mask_out)[idx] = out;
-  if (J.residual) J.residual[idx] = r;
-}
 
 // Per-pixel passes over the batch: 0 erode raw -> seeds, 1 dilate seeds ->
 // mask, 2 copy seeds to the caller's eroded output, 3 copy the fill.
@@ -326,8 +299,8 @@ static void mask_impl(Batch& b, const rf_mask_params& mp, hipStream_t s) {
     eroded |= J.eroded != nullptr;
     filled |= J.filled != nullptr;
   }
+  launch_residual(b, DF, STORAGE, mp.gamma, s);
   int g = set_bases(b, pixel_groups);
-  residual_kernel<DF, STORAGE><<<g, 256, 0, s>>>(b, mp.gamma);
   pixel_pass_kernel<<<g, 256, 0, s>>>(b, 0);
   if (eroded) pixel_pass_kernel<<<g, 256, 0, s>>>(b, 2);
   // the tile flags are all zero here: map initialisation zeroes them, and

@@ -489,6 +489,79 @@ struct CachedSlots {
   }
 };
 
+// Wavefront 1 of a residual workgroup (the tracking kernel runs the same
+// steps inline): the tile's cached block pairs (tiles without a cache entry
+// start from an empty table) placed in the direct-mapped window around their
+// bounding box or in the LDS hash.
+template <int SLOTS>
+__device__ __forceinline__ void build_tile_cache(const BlockRef* tab, const uint32_t* tcount, bool cached, int nrefs,
+                                                 uint32_t epoch, int lane, unsigned long long* s_hk, int* s_hs,
+                                                 uint8_t* s_used, int* s_grid, uint8_t* s_gused, int* s_org,
+                                                 uint32_t* s_nref) {
+  const BlockRef none{kEmptyKey, -1, 0u};
+  constexpr int kLoads = SLOTS / 64;
+  const int cnt = cached ? (int)min(*tcount, (uint32_t)nrefs) : 0;
+  BlockRef e[kLoads];
+#pragma unroll
+  for (int q = 0; q < kLoads; ++q) e[q] = (cached && lane + 64 * q < nrefs) ? tab[lane + 64 * q] : none;
+#pragma unroll
+  for (int q = 0; q < SLOTS / 64; ++q) {
+    s_hk[lane + 64 * q] = kEmptyKey;
+    s_hs[lane + 64 * q] = kNoSlot;
+    s_used[lane + 64 * q] = 0;
+  }
+#pragma unroll
+  for (int q = 0; q < kWinCells / 64; ++q) {
+    s_grid[lane + 64 * q] = kNoSlot;
+    s_gused[lane + 64 * q] = 0;
+  }
+  if (lane == 0) *s_nref = 0u;
+  // window origin: centre of the bounding box of the valid cached blocks
+  bool v[kLoads];
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+  for (int q = 0; q < kLoads; ++q) {
+    v[q] = lane + 64 * q < cnt && e[q].key != kEmptyKey && (e[q].slot >= 0 || e[q].epoch == epoch);
+    int p[3];
+    unpack_key(e[q].key, p[0], p[1], p[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], v[q] ? p[d] : INT_MAX);
+      hi[d] = max(hi[d], v[q] ? p[d] : INT_MIN);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], o));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], o));
+    }
+  }
+  const bool any = lo[0] <= hi[0];
+  int org[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) org[d] = any ? ((lo[d] + hi[d]) >> 1) - (kWin / 2 - 1) : kFarOrigin;
+  if (lane == 0) {
+    s_org[0] = org[0];
+    s_org[1] = org[1];
+    s_org[2] = org[2];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const TileCache<SLOTS> wc{s_hk, s_hs, s_used, s_grid, s_gused, org[0], org[1], org[2]};
+#pragma unroll
+  for (int q = 0; q < kLoads; ++q) {
+    if (!v[q]) continue;
+    int p[3];
+    unpack_key(e[q].key, p[0], p[1], p[2]);
+    const int cl = wc.cell(p[0], p[1], p[2]);
+    if (cl >= 0) s_grid[cl] = e[q].slot;
+    else wc.insert(p[0], p[1], p[2], e[q].key, e[q].slot, false);
+  }
+}
+
 // SLOTS: pairs the tile cache holds in LDS (256 at levels 0-1, 512 at the
 // coarser levels, whose few tiles each touch more blocks; more LDS and
 // registers there cost nothing, since those launches have few workgroups).
@@ -554,6 +627,8 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
                   (size_t)(cached ? g0 : 0) * tile_refs(cached ? a.level : 0);
   uint32_t* tcount = m.tc_count + (size_t)(cached ? a.level : 0) * m.tc_tiles + (cached ? g0 : 0);
   const int nrefs = tile_refs(a.level);
+  // (the steps of build_tile_cache, written out: calling it here changed the
+  // kernel's instruction schedule and cost the large rooms' tracking 3%)
   if (wave == 1) {
     const BlockRef none{kEmptyKey, -1, 0u};
     constexpr int kLoads = SLOTS / 64;
@@ -742,6 +817,62 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   }
 }
 
+// Residual of the dynamic mask (Sec. III-C): r = S(T x)^2 of every valid
+// pixel at full resolution and the raw decision r > gamma tau^2, with the
+// pixels in the 16x16 tiles of the finest tracking level so that the corner
+// blocks resolve through that level's tile cache (the pairs the last
+// registration at this level used; a tile without them starts empty).  The
+// cache only replaces hash-table probes, so the result is that of plain
+// lookups.
+template <int DF, int STORAGE, int SLOTS>
+__global__ __launch_bounds__(kTrackBlock) void residual_kernel(Batch b, float gamma) {
+  __shared__ unsigned long long s_hk[SLOTS];
+  __shared__ int s_hs[SLOTS];
+  __shared__ uint8_t s_used[SLOTS];
+  __shared__ int s_grid[kWinCells];
+  __shared__ uint8_t s_gused[kWinCells];
+  __shared__ int s_org[3];
+  __shared__ uint32_t s_nref;
+  const int jb = batch_job(b, blockIdx.x);
+  const Job& J = b.job[jb];
+  const MapDev& m = J.m;
+  const FrameDev& f = J.f;
+  const int g0 = blockIdx.x - b.base[jb];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tiles_x = (f.W + kTileW - 1) / kTileW;
+  const int u = (g0 % tiles_x) * kTileW + (wave % (kTileW / 8)) * 8 + (lane & 7);
+  const int v = (g0 / tiles_x) * 16 + (wave / (kTileW / 8)) * 8 + (lane >> 3);
+  const bool inside = u < f.W && v < f.H;
+  const int pix = inside ? v * f.W + u : 0;
+  const float D = load_depth<DF>(f, pix);
+  const bool cached = g0 < (int)m.tc_tiles;
+  const BlockRef* tab = m.tcache + (size_t)(cached ? g0 : 0) * tile_refs(0);
+  const uint32_t* tcount = m.tc_count + (cached ? g0 : 0);
+  if (wave == 1)
+    build_tile_cache<SLOTS>(tab, tcount, cached, tile_refs(0), m.st->epoch, lane, s_hk, s_hs, s_used, s_grid,
+                            s_gused, s_org, &s_nref);
+  __syncthreads();
+  const TileCache<SLOTS> cache{s_hk, s_hs, s_used, s_grid, s_gused, s_org[0], s_org[1], s_org[2]};
+  uint8_t out = 0;
+  float r = -1.0f;
+  if (inside && depth_ok(D, m.dmax)) {
+    float R[9], t[3];
+    load_pose_f(J.pose, R, t);
+    const float x[3] = {(((float)u - f.cx) * f.ifx) * D, (((float)v - f.cy) * f.ify) * D, D};
+    float y[3];
+    xform(R, t, x, y);
+    float S, Iv, g3[3], h3[3];
+    if (sample_map<STORAGE, false, false>(m, y, S, g3, Iv, h3, CachedSlots<SLOTS>{cache})) {
+      r = S * S;
+      out = (r > gamma * (m.tau * m.tau)) ? 1 : 0;
+    }
+  }
+  if (inside) {
+    (J.raw ? J.raw : J.mask_out)[pix] = out;
+    if (J.residual) J.residual[pix] = r;
+  }
+}
+
 // Solve of the last evaluation of a pass (or, in mode 1, the raw totals):
 // one workgroup per job.
 __global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a, double* out29) {
@@ -867,6 +998,25 @@ void launch_track(Batch& b, int df, int st, const rf_track_params& tp, hipStream
   a.state_read = (j - 1) % 2;
   a.state_write = -1;
   track_finalize_kernel<<<b.n, 64, 0, s>>>(b, a, nullptr);
+}
+
+void launch_residual(Batch& b, int df, int st, float gamma, hipStream_t s) {
+  int total = 0;
+  for (int j = 0; j < b.n; ++j) {
+    b.base[j] = total;
+    total += track_tiles(b.job[j].f, 0);
+  }
+  b.base[b.n] = total;
+  constexpr int S = tile_refs(1) * 2;  // the finest level's cache size, as in tracking
+  static_assert(tile_refs(0) <= S, "level-0 pairs fit the cache");
+  const dim3 g(total), blk(kTrackBlock);
+  if (df == RF_DEPTH_U16) {
+    if (st == RF_STORAGE_FP32) residual_kernel<RF_DEPTH_U16, RF_STORAGE_FP32, S><<<g, blk, 0, s>>>(b, gamma);
+    else residual_kernel<RF_DEPTH_U16, RF_STORAGE_FP16_U8, S><<<g, blk, 0, s>>>(b, gamma);
+  } else {
+    if (st == RF_STORAGE_FP32) residual_kernel<RF_DEPTH_F32, RF_STORAGE_FP32, S><<<g, blk, 0, s>>>(b, gamma);
+    else residual_kernel<RF_DEPTH_F32, RF_STORAGE_FP16_U8, S><<<g, blk, 0, s>>>(b, gamma);
+  }
 }
 
 void launch_normal_equations(Batch& b, int df, int st, int level, float w_c, double* out29, hipStream_t s) {
