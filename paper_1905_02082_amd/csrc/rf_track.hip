@@ -19,7 +19,9 @@
 // other workgroups: the solve of iteration j runs at the start of launch j+1,
 // redundantly in every workgroup (all read the same completed totals and run
 // the same instructions, so all obtain the same pose), overlapped with the
-// pose-independent loads of the pixel.  Accumulators rotate through three
+// pose-independent loads of the pixel (levels with more workgroups than two
+// resident rounds solve in a one-workgroup launch instead, see
+// kSeparateSolveTiles).  Accumulators rotate through three
 // buffers (read j-1, write j, clear j+1) and the pose through two, so no
 // launch reads what the same launch writes.  A one-workgroup finalize launch
 // solves the last iteration and writes the caller's pose.
@@ -48,7 +50,7 @@ struct TrackArgs {
   int prev_first;    // it was the first iteration of its level
   int acc_read, acc_write, acc_clear;  // accumulator buffer indices (-1: none)
   int pose_read, pose_write;           // 0/1: pose scratch, 2: caller's pose (-1: none)
-  int mode;          // 0: track; 1: write the normal equations of acc_read to out29
+  int mode;          // 0: track; 1: write the normal equations of acc_read to out29; 2: solve only
   int adaptive;      // 1: Levenberg-Marquardt (accept / reject, adaptive lambda); 0: fixed lambda
   int state_read, state_write;         // Levenberg-Marquardt state buffers (0/1, -1: none)
 };
@@ -700,7 +702,8 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
       const double* Tin = pose_buf(m, user_pose, a.pose_read);
       if (threadIdx.x < 16) {
         s_T[threadIdx.x] = Tin[threadIdx.x];
-        if (g0 == 0 && !stopped) pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
+        if (g0 == 0 && !stopped && a.pose_write >= 0)
+          pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
       }
       if (LM && g0 == 0 && !stopped && a.state_write >= 0) {
         // the starting pose is the accepted one until the first decision
@@ -873,8 +876,9 @@ __global__ __launch_bounds__(kTrackBlock) void residual_kernel(Batch b, float ga
   }
 }
 
-// Solve of the last evaluation of a pass (or, in mode 1, the raw totals):
-// one workgroup per job.
+// Solve of the last evaluation of a pass (mode 0), the raw totals (mode 1),
+// or, for launches with many workgroups, the solve a tracking launch would
+// otherwise run at its start (mode 2): one workgroup per job.
 __global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a, double* out29) {
   __shared__ double s_ne[kNE];
   __shared__ double s_nc[kLmWords];
@@ -890,7 +894,13 @@ __global__ __launch_bounds__(64) void track_finalize_kernel(Batch b, TrackArgs a
   }
   if (m.st->track_stop) {
     // stopped earlier: both scratch poses hold the last good pose
-    if (threadIdx.x < 16) user_pose[threadIdx.x] = pose_buf(m, user_pose, a.pose_read)[threadIdx.x];
+    if (a.mode == 0 && threadIdx.x < 16) user_pose[threadIdx.x] = pose_buf(m, user_pose, a.pose_read)[threadIdx.x];
+    return;
+  }
+  if (a.mode == 2) {
+    // the solve a tracking launch would run at its start, once per job
+    if (a.adaptive) solve_step<true>(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true, false, false, s_nc, s_st);
+    else solve_step<false>(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true, false, false, s_nc, s_st);
     return;
   }
   if (a.adaptive) solve_step<true>(m, user_pose, a, J.stats, s_ne, s_T, &s_state, true, false, true, s_nc, s_st);
@@ -916,6 +926,14 @@ __global__ void track_reset_kernel(Batch b) {
     }
   }
 }
+
+// Tracking levels whose launches have more workgroups than this (all jobs
+// together; two resident rounds of the chip) solve in a launch of their own,
+// once per job, instead of redundantly at the start of every workgroup: with
+// many workgroups the redundant solves and the reads of the accumulator
+// copies they share cost more than the extra launch.  Both schedules run the
+// same solve on the same totals, so the poses are identical.
+constexpr int kSeparateSolveTiles = 3072;
 
 static int track_tiles(const FrameDev& f, int level) {
   const int wl = (f.W + (1 << level) - 1) >> level;
@@ -958,7 +976,10 @@ static void track_dispatch(Batch& b, int df, int st, const TrackArgs& a, hipStre
 void launch_track(Batch& b, int df, int st, const rf_track_params& tp, hipStream_t s) {
   track_reset_kernel<<<b.n, 256, 0, s>>>(b);
   int j = 0, prev_level = -1, prev_first = 0;
-  for (int l = tp.levels - 1; l >= 0; --l)
+  for (int l = tp.levels - 1; l >= 0; --l) {
+    int tiles = 0;
+    for (int q = 0; q < b.n; ++q) tiles += track_tiles(b.job[q].f, l);
+    const bool separate = tiles > kSeparateSolveTiles;
     for (int it = 0; it < tp.iters_per_level; ++it, ++j) {
       TrackArgs a{};
       a.level = l;
@@ -977,10 +998,21 @@ void launch_track(Batch& b, int df, int st, const rf_track_params& tp, hipStream
       a.adaptive = tp.adaptive;
       a.state_read = j > 0 ? (j - 1) % 2 : -1;
       a.state_write = j % 2;
+      if (separate && a.solve) {
+        // the solve once per job, then the evaluation at the pose it wrote
+        TrackArgs c = a;
+        c.mode = 2;
+        track_finalize_kernel<<<b.n, 64, 0, s>>>(b, c, nullptr);
+        a.solve = 0;
+        a.pose_read = j % 2;
+        a.pose_write = -1;
+        a.state_write = -1;
+      }
       track_dispatch(b, df, st, a, s);
       prev_level = l;
       prev_first = it == 0;
     }
+  }
   if (j == 0) return;
   TrackArgs a{};
   a.level = -1;
