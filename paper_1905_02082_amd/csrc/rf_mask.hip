@@ -10,7 +10,7 @@
 //                     marks that tile dirty; a few more parallel passes
 //                     re-run only the dirty tiles (most marks made while
 //                     neighbours grew concurrently resolve here)
-//   flood_finish      one workgroup re-runs dirty tiles one at a time until
+//   flood_finish      one workgroup re-runs dirty tiles, four at a time, until
 //                     no tile is dirty: growth is monotone, so the result is
 //                     the unique least fixpoint the queue of Algorithm 1
 //                     reaches, with no grid-wide barrier
@@ -65,22 +65,29 @@ constexpr int kHalo = kTile + 2;
 constexpr int kFloodPasses = 5;  // parallel passes over dirty tiles before the one-workgroup drain
 
 // Grows the seeds of tile (tx,ty) to the tile-local fixpoint.  The halo is
-// read-only input.  Returns (in LDS) whether anything changed; marks the
-// neighbouring tiles that a newly set border pixel can reach.
+// read-only input.  Marks the neighbouring tiles that a newly set border
+// pixel can reach.  The workgroup may hold several groups of nthr threads
+// (tid: index in the group), each on a tile of its own with its own LDS
+// buffers and flag, all passing the same barriers; a group with active =
+// false takes part in the barriers only.  Two groups may hold neighbouring
+// tiles: each writes only its own tile's pixels, and a new member on a border
+// marks the neighbour, which the caller then runs again, so the result is the
+// same least fixpoint.
 template <int DF>
-__device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, int tx, int ty, int tiles_x,
-                               int tiles_y, uint8_t* s_m, uint8_t* s_m0, float* s_d, int* s_flag,
-                               uint32_t* mark) {
-  const int nthr = blockDim.x;
+__device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, int tx, int ty, bool active,
+                               int tiles_x, int tiles_y, uint8_t* s_m, uint8_t* s_m0, float* s_d, int* s_flag,
+                               int* s_any, uint32_t* mark, int tid, int nthr) {
   const int u0 = tx * kTile - 1, v0 = ty * kTile - 1;
-  for (int i = threadIdx.x; i < kHalo * kHalo; i += nthr) {
-    const int hu = i % kHalo, hv = i / kHalo;
-    const int u = u0 + hu, v = v0 + hv;
-    const bool in = (u >= 0 && v >= 0 && u < f.W && v < f.H);
-    const uint8_t mv = in ? (m.md[v * f.W + u] != 0) : 0;
-    s_m[i] = mv;
-    s_m0[i] = mv;
-    s_d[i] = flood_depth<DF>(f, m.dmax, u, v);
+  if (active) {
+    for (int i = tid; i < kHalo * kHalo; i += nthr) {
+      const int hu = i % kHalo, hv = i / kHalo;
+      const int u = u0 + hu, v = v0 + hv;
+      const bool in = (u >= 0 && v >= 0 && u < f.W && v < f.H);
+      const uint8_t mv = in ? (m.md[v * f.W + u] != 0) : 0;
+      s_m[i] = mv;
+      s_m0[i] = mv;
+      s_d[i] = flood_depth<DF>(f, m.dmax, u, v);
+    }
   }
   __syncthreads();
   // Local fixpoint.  A parallel pass over all pixels (every non-member checks
@@ -90,10 +97,11 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
   // the three neighbours on the side already swept, so one sweep carries a
   // path that is monotone in its direction across the tile.
   for (;;) {
-    if (threadIdx.x == 0) *s_flag = 0;
+    if (tid == 0) *s_flag = 0;
+    if (threadIdx.x == 0) *s_any = 0;
     __syncthreads();
     int changed = 0;
-    for (int i = threadIdx.x; i < kTile * kTile; i += nthr) {
+    for (int i = tid; active && i < kTile * kTile; i += nthr) {
       const int hu = 1 + (i % kTile), hv = 1 + (i / kTile);
       const int c = hv * kHalo + hu;
       if (s_m[c]) continue;
@@ -116,19 +124,22 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
         changed = 1;
       }
     }
-    if (changed) *s_flag = 1;
+    if (changed) {
+      *s_flag = 1;
+      *s_any = 1;
+    }
     __syncthreads();
-    const int again = *s_flag;
+    const int again = *s_flag, any = *s_any;
     __syncthreads();
-    if (!again) break;
+    if (!any) break;
     // Wavefront w (0..3) sweeps direction w; lane t walks line t.  The three
     // neighbours on the swept side are the lane's own previous cell and its
     // two neighbouring lanes' previous cells, taken from registers by
     // shuffles (the halo lines from LDS), so a step costs no LDS round trip.
     // The four sweeps run concurrently: growth is monotone and the check
     // above runs again after them, so the fixpoint is the same.
-    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
-    if (w < 4 && t < kTile) {
+    const int t = tid & 63;
+    for (int w = tid >> 6; again && w < 4 && t < kTile; w += (nthr >> 6)) {
       const int along = (w < 2) ? 1 : kHalo;   // next cell along the line
       const int across = (w < 2) ? kHalo : 1;  // next line
       const int sgn = (w & 1) ? -1 : 1;
@@ -169,7 +180,7 @@ __device__ void flood_one_tile(const MapDev& m, const FrameDev& f, float theta, 
     __syncthreads();
   }
   // write back new members; mark neighbours a new border member can reach
-  for (int i = threadIdx.x; i < kTile * kTile; i += nthr) {
+  for (int i = tid; active && i < kTile * kTile; i += nthr) {
     const int lu = i % kTile, lv = i / kTile;
     const int c = (lv + 1) * kHalo + (lu + 1);
     if (!s_m[c] || s_m0[c]) continue;
@@ -203,7 +214,7 @@ template <int DF>
 __global__ __launch_bounds__(256) void flood_tiles_kernel(Batch b, float theta, int pass) {
   __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
   __shared__ float s_d[kHalo * kHalo];
-  __shared__ int s_flag;
+  __shared__ int s_flag, s_any;
   const int jb = batch_job(b, blockIdx.x);
   const Job& J = b.job[jb];
   const MapDev& m = J.m;
@@ -226,16 +237,20 @@ __global__ __launch_bounds__(256) void flood_tiles_kernel(Batch b, float theta, 
     }
     if (!__syncthreads_or(any)) return;
   }
-  flood_one_tile<DF>(m, f, theta, tx, ty, J.tiles_x, J.tiles_y, s_m, s_m0, s_d, &s_flag, mark);
+  flood_one_tile<DF>(m, f, theta, tx, ty, true, J.tiles_x, J.tiles_y, s_m, s_m0, s_d, &s_flag, &s_any, mark,
+                     threadIdx.x, blockDim.x);
 }
 
 // One workgroup per job: process dirty tiles until none is left (or the
-// work cap).
+// work cap), kFinishGroups tiles at a time (groups of kFinishThreads threads;
+// 4 measured faster than 8 or 16 smaller groups).
+constexpr int kFinishGroups = 4;
+constexpr int kFinishThreads = 1024 / kFinishGroups;
 template <int DF>
 __global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta, int buf) {
-  __shared__ uint8_t s_m[kHalo * kHalo], s_m0[kHalo * kHalo];
-  __shared__ float s_d[kHalo * kHalo];
-  __shared__ int s_flag;
+  __shared__ uint8_t s_m[kFinishGroups][kHalo * kHalo], s_m0[kFinishGroups][kHalo * kHalo];
+  __shared__ float s_d[kFinishGroups][kHalo * kHalo];
+  __shared__ int s_flag[kFinishGroups], s_any;
   __shared__ int s_list[1024];
   __shared__ int s_n;
   const Job& J = b.job[blockIdx.x];
@@ -261,10 +276,12 @@ __global__ __launch_bounds__(1024) void flood_finish_kernel(Batch b, float theta
     const int n = min(s_n, 1024);
     __syncthreads();
     if (n == 0) break;
-    for (int k = 0; k < n; ++k) {
-      const int tile = s_list[k];
-      flood_one_tile<DF>(m, f, theta, tile % tiles_x, tile / tiles_x, tiles_x, tiles_y, s_m, s_m0, s_d, &s_flag,
-                         dirty);
+    const int q = threadIdx.x / kFinishThreads;  // group
+    for (int k = 0; k < n; k += kFinishGroups) {
+      const bool act = k + q < n;
+      const int tile = act ? s_list[k + q] : 0;
+      flood_one_tile<DF>(m, f, theta, tile % tiles_x, tile / tiles_x, act, tiles_x, tiles_y, s_m[q], s_m0[q],
+                         s_d[q], &s_flag[q], &s_any, dirty, threadIdx.x % kFinishThreads, kFinishThreads);
     }
     processed += n;
     if (processed > max_tiles_processed) {

@@ -256,6 +256,40 @@ def test_dynamic_mask_stages_bit_exact(rf, dyn_small, k):
     assert ref["raw"].sum() > 20 and ref["final"].sum() > ref["eroded"].sum()
 
 
+def test_flood_fill_across_the_whole_frame(rf):
+    """A map of a fronto-parallel wall at 2 m; the frame sees a plane slanted
+    from 1.90 m (top left) to 2.50 m (bottom right): only a corner lies in
+    front of the wall by more than the residual threshold, and the flood fill
+    grows from its eroded seeds over the whole plane (neighbouring depths
+    differ by ~1 mm, far below theta D), about 35 tile steps, so most of the
+    growth is left to the one-workgroup drain after the parallel passes.  All
+    mask stages are bit-exact against the FP32 mirror."""
+    W, H = 640, 480
+    intr = (525.0, 525.0, 319.5, 239.5)
+    rgb = np.full((H, W, 3), 128, np.uint8)
+    wall = np.full((H, W), 2.0, np.float32)
+    uu, vv = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    slant = (1.90 + 0.6 * (uu / (W - 1) + vv / (H - 1)) / 2.0).astype(np.float32)
+    T = np.eye(4)
+    params = rf.MapParams(0.01, 0.03, 5.0, 1 << 16, 1 << 14, 255, 2, "fp32", W * H)
+    m = rf.Map(params)
+    g0 = rf.Frame.from_numpy(wall, rgb, *intr)
+    P = dev_pose(T)
+    m.allocate(g0, P)
+    m.integrate(g0, P)
+    o32 = O.OracleMap(0.01, 0.03, 5.0, 255, 2, real_bits=32)
+    f0 = O.Frame(wall, rgb, *intr)
+    o32.allocate(f0, T)
+    o32.integrate(f0, T)
+    g1 = rf.Frame.from_numpy(slant, rgb, *intr)
+    out = m.dynamic_mask(g1, P, rf.MaskParams(0.5, 0.007), stages=True)
+    ref = o32.mask(O.Frame(slant, rgb, *intr), T, 0.5, 0.007)
+    for key in ("raw", "eroded", "filled", "final"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+    assert 0 < ref["eroded"].sum() < 0.05 * W * H and ref["filled"].sum() > 0.9 * W * H
+    assert m.status()[0] == 0
+
+
 # ---------------------------------------------------------------- surface / checkpoint
 
 def test_extract_surface_matches_mirror(rf, room):
