@@ -142,8 +142,8 @@ __device__ __forceinline__ int tri_index(int i, int j) {  // H(i,j), i <= j, pac
   return 6 * i - (i * (i - 1)) / 2 + (j - i);
 }
 
-// Wavefront 0 of a workgroup: totals -> delta by row-parallel elimination
-// (lane r holds row r of [H + lambda diag H | -g]; no pivoting, H is
+// The solving wavefront of a workgroup: totals -> delta by row-parallel
+// elimination (lane r holds row r of [H + lambda diag H | -g]; no pivoting, H is
 // symmetric positive semi-definite) -> exp(delta^) T.  Writes the new pose
 // (row-major 12 values) to s_T and the outcome to *s_state:
 // 0 ok, RF_FLAG_TRACK_FEW_PIXELS or RF_FLAG_TRACK_SINGULAR (pose kept).
@@ -153,7 +153,7 @@ __device__ __forceinline__ int tri_index(int i, int j) {  // H(i,j), i <= j, pac
 // lanes < 16 (element (er, ec) = (lane / 4, lane % 4) of the input pose).
 __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const double tin[4], double* s_T,
                                   int* s_state) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   int state = 0;
   bool finite = true;
 #pragma unroll
@@ -252,8 +252,8 @@ __device__ void solve_update_wave(const double* s_ne, const TrackArgs& a, const 
   if (lane == 0) *s_state = state;
 }
 
-// The solve step shared by the tracking and finalize launches, run by
-// wavefront 0: reads the accumulated totals, solves, and (workgroup 0 only)
+// The solve step shared by the tracking and finalize launches, run by the
+// solving wavefront: reads the accumulated totals, solves, and (workgroup 0 only)
 // publishes the pose, the statistics and, on a degenerate system, the stop
 // flag.  Returns through LDS: s_T (new pose), *s_state.
 //
@@ -269,7 +269,7 @@ template <bool LM>
 __device__ void solve_step(const MapDev& m, double* user_pose, const TrackArgs& a, rf_track_stats* stats,
                            double* s_ne, double* s_T, int* s_state, bool publish, bool stopped, bool final_only,
                            double* s_nc, double* s_st) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int ec = lane & 3;
   // the input pose is fetched together with the totals (one round trip)
   double tin[4] = {0.0, 0.0, 0.0, 0.0};
@@ -622,8 +622,8 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
     const int q1 = min(g0 * per + per, kUsedWords);
     for (int q = g0 * per + threadIdx.x; q < q1; q += kTrackBlock) *used_word(acc_buf(m, a.acc_clear), q) = 0ull;
   }
-  // the tile's cached block pairs (wavefront 1, while wavefront 0 solves);
-  // tiles without a cache entry start from an empty table
+  // the tile's cached block pairs (the wavefront after the solving one,
+  // while it solves); tiles without a cache entry start from an empty table
   const bool cached = a.level < kCacheLevels && g0 < (int)m.tc_tiles;
   BlockRef* tab = m.tcache + (size_t)m.tc_tiles * tile_refs_before(cached ? a.level : 0) +
                   (size_t)(cached ? g0 : 0) * tile_refs(cached ? a.level : 0);
@@ -631,7 +631,11 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
   const int nrefs = tile_refs(a.level);
   // (the steps of build_tile_cache, written out: calling it here changed the
   // kernel's instruction schedule and cost the large rooms' tracking 3%)
-  if (wave == 1) {
+  // the solving wavefront (and the cache builder after it) rotate with the
+  // tile index, so the solves of the workgroups sharing a CU spread over its
+  // SIMDs
+  const int sw = g0 & 3, cw = (sw + 1) & 3;
+  if (wave == cw) {
     const BlockRef none{kEmptyKey, -1, 0u};
     constexpr int kLoads = SLOTS / 64;
     const int cnt = cached ? (int)min(*tcount, (uint32_t)nrefs) : 0;
@@ -695,23 +699,22 @@ __global__ __launch_bounds__(kTrackBlock) void track_kernel(Batch b, TrackArgs a
       else wc.insert(p[0], p[1], p[2], e[q].key, e[q].slot, false);
     }
   }
-  if (threadIdx.x < 64) {
+  if (wave == sw) {
     if (a.solve) {
       solve_step<LM>(m, user_pose, a, stats, s_ne, s_T, &s_state, g0 == 0, stopped != 0, false, s_nc, s_st);
     } else {
       const double* Tin = pose_buf(m, user_pose, a.pose_read);
-      if (threadIdx.x < 16) {
-        s_T[threadIdx.x] = Tin[threadIdx.x];
-        if (g0 == 0 && !stopped && a.pose_write >= 0)
-          pose_buf(m, user_pose, a.pose_write)[threadIdx.x] = Tin[threadIdx.x];
+      if (lane < 16) {
+        s_T[lane] = Tin[lane];
+        if (g0 == 0 && !stopped && a.pose_write >= 0) pose_buf(m, user_pose, a.pose_write)[lane] = Tin[lane];
       }
       if (LM && g0 == 0 && !stopped && a.state_write >= 0) {
         // the starting pose is the accepted one until the first decision
         double* S = lm_state(m, a.state_write);
-        if (threadIdx.x < 16) S[threadIdx.x] = Tin[threadIdx.x];
-        if (threadIdx.x == 0) S[45] = a.lm_lambda;
+        if (lane < 16) S[lane] = Tin[lane];
+        if (lane == 0) S[45] = a.lm_lambda;
       }
-      if (threadIdx.x == 0) s_state = 0;
+      if (lane == 0) s_state = 0;
     }
   }
   __syncthreads();
