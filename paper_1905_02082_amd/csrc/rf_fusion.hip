@@ -11,8 +11,8 @@
 // list, each touched block once.
 //
 // Integration: workgroups stride over the listed blocks, 256 threads x 2
-// voxels per block, two blocks per step, the next step's list entries and
-// buckets fetched during the current one; only voxels the frame updates are
+// voxels per block, two blocks per step, each workgroup's list entries and
+// buckets read into LDS up front; only voxels the frame updates are
 // written.  Records are SoA per block, so a workgroup's loads and stores are
 // contiguous 4-KiB (FP32) / 2-KiB (FP16) runs.
 #include <type_traits>
@@ -482,33 +482,14 @@ __global__ __launch_bounds__(256) void classify_kernel(Batch b) {
 // Integration of one frame into the blocks of the frame list (Sec. III-A
 // running average, Sec. III-D carving).  Workgroups stride over the list and
 // take kIntegBlocks listed blocks per step; a thread owns voxels l and l + 256
-// of each.  The list entries and buckets of a step (uniform) are fetched
-// during the step before it; a step issues the depth, the mask byte and the
+// of each.  A workgroup's list entries and buckets (uniform) are read into
+// LDS before its steps; a step issues the depth, the mask byte and the
 // voxel record of every voxel together before any is used.  The record is
 // read even for voxels the frame leaves untouched (about a fifth of a listed
 // block), which costs those bytes but saves a dependent round trip; only
 // voxels the frame updates are written.
 constexpr int kIntegBlocks = 2;
-
-// Bucket i (key, slot) of the wavefront's lane i, for i < N.
-template <int N>
-__device__ __forceinline__ void take_lanes(unsigned long long key, uint32_t slot, Bucket (&out)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)key, i);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(key >> 32), i);
-    out[i].key = ((unsigned long long)hi << 32) | lo;
-    out[i].slot = __builtin_amdgcn_readlane(slot, i);
-  }
-}
-
-// Whole-block test outcome (top bits of the frame-list entry) held by the
-// wavefront's lane i.
-template <int N>
-__device__ __forceinline__ void take_state(uint32_t bits, uint32_t (&out)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) out[i] = __builtin_amdgcn_readlane(bits, i);
-}
+constexpr int kIntegTab = 256;  // listed blocks a workgroup holds in LDS at a time
 
 // COMPACT: some job of the batch keeps compact free space (its frame-list
 // entries carry the whole-block test's outcome); without it those paths are
@@ -532,7 +513,6 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   float R[9], t[3];
   load_pose_f(J.pose, R, t);
   uint32_t nb = 0, nf = 0;
-  const uint32_t stride = kIntegBlocks * gn;
   // correctly rounded reciprocals 1 / (W + 1) of the weights 0 .. 255
   __shared__ float s_rw[256];
   // compact free space: per pending free block of the step, its voxels'
@@ -543,49 +523,48 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
   s_rw[threadIdx.x] = 1.0f / (float)(threadIdx.x + 1);
   if (threadIdx.x < kIntegBlocks) s_pf[threadIdx.x] = 0u;
   __syncthreads();
-  // The list entries and buckets of a step are fetched during the step before
-  // it (the list entries while its voxel gathers are in flight, the buckets
-  // after them), so a step waits on two round trips instead of four.  Lane i
-  // of each wavefront fetches listed block i (i < kIntegBlocks; the other
-  // lanes repeat the last), and the step reads the buckets out of lane i once
-  // its colour loads have returned, before its stores of colour, so the next
-  // step starts without waiting for those stores.
-  const int lane = threadIdx.x & 63;
-  const uint32_t my_i = (uint32_t)min(lane, kIntegBlocks - 1);
   // work-list entries of compact free-space maps carry the whole-block
   // test's outcome in their top bits (compact maps keep bucket indices below
   // 2^22); frame-list entries are plain bucket indices
   const uint32_t bucket_bits = wl ? kEntryBucket : 0xFFFFFFFFu;
-  Bucket cur[kIntegBlocks];
-  uint32_t cur_e[kIntegBlocks];
-  if (g0 < nF) {
-    const uint32_t fi = g0 + my_i * gn;
-    const uint32_t e = list[fi < nF ? fi : g0];
-    const Bucket bq = m.buckets[e & bucket_bits];
-    take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
-    take_state<kIntegBlocks>(e, cur_e);
-  }
-  for (uint32_t f0 = g0; f0 < nF; f0 += stride) {
+  // The workgroup's listed blocks (entries g0, g0 + gn, ...) are read in
+  // chunks of kIntegTab, list entries and then their buckets into LDS (two
+  // round trips per chunk, the whole share of most workgroups), so a step
+  // finds its blocks there and waits only on its voxel gathers.
+  __shared__ unsigned long long s_tkey[kIntegTab];
+  __shared__ uint32_t s_tslot[kIntegTab], s_tent[kIntegTab];
+  const uint32_t nmine = g0 < nF ? (nF - g0 + gn - 1) / gn : 0u;  // entries of this workgroup
+  for (uint32_t k0 = 0; k0 < nmine; k0 += kIntegTab) {
+    const uint32_t nk = min(nmine - k0, (uint32_t)kIntegTab);
+    __syncthreads();  // the previous chunk's steps are done with the table
+    for (uint32_t q = threadIdx.x; q < nk; q += blockDim.x) {
+      const uint32_t e = list[g0 + (k0 + q) * gn];
+      const Bucket bq = m.buckets[e & bucket_bits];
+      s_tkey[q] = bq.key;
+      s_tslot[q] = bq.slot;
+      s_tent[q] = e;
+    }
+    __syncthreads();
+  for (uint32_t k = 0; k < nk; k += kIntegBlocks) {
     Bucket bu[kIntegBlocks];
     uint32_t st[kIntegBlocks];  // uniform: the whole-block test's outcome
     uint32_t eb[kIntegBlocks];  // uniform: bucket index
     bool live[kIntegBlocks], whole[kIntegBlocks], pend[kIntegBlocks];
 #pragma unroll
     for (int i = 0; i < kIntegBlocks; ++i) {
-      bu[i] = cur[i];
-      st[i] = COMPACT ? (cur_e[i] & ~bucket_bits) : 0u;
-      eb[i] = cur_e[i] & bucket_bits;
+      const bool in = k + i < nk;
+      const uint32_t ki = in ? k + i : k;
+      const uint32_t e = s_tent[ki];
+      bu[i].key = s_tkey[ki];
+      bu[i].slot = s_tslot[ki];
+      st[i] = COMPACT ? (e & ~bucket_bits) : 0u;
+      eb[i] = e & bucket_bits;
       whole[i] = (st[i] & kEntryWhole) != 0u;
       // a free block: evaluated voxel by voxel from its free value, it takes
       // a pool slot below if a voxel gets a band update
       pend[i] = (st[i] & (kEntryWhole | kEntryFresh)) == kEntryFresh;
-      live[i] = f0 + i * gn < nF && (bu[i].slot < m.max_blocks || pend[i]);
+      live[i] = in && (bu[i].slot < m.max_blocks || pend[i]);
     }
-    // the next step's list entries (past the list's end: this step's first
-    // entry again, so the loads stay unconditional and in bounds)
-    const uint32_t f1 = f0 + stride;
-    const uint32_t fn = f1 + my_i * gn;
-    const uint32_t hn = list[fn < nF ? fn : f0];
     int pix[NV];
     uint32_t vidx[NV];
     float X2[NV];
@@ -656,7 +635,6 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       rw[v] = s_rw[tab ? wi : 0];
       if (!tab) rw[v] = 1.0f / (W[v] + 1.0f);
     }
-    const Bucket bq = m.buckets[hn & bucket_bits];  // the next step's buckets
     // the per-voxel rule's decision and the new sdf of every voxel
     bool band[NV], upd[NV];
     float nsdf[NV];
@@ -761,8 +739,6 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]), "+v"(cpx[v][2]));
-    take_lanes<kIntegBlocks>(bq.key, bq.slot, cur);
-    take_state<kIntegBlocks>(hn, cur_e);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if (!band[v]) continue;
@@ -774,6 +750,7 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
                                                             Wn, rw[v]))));
       m.rgb[vidx[v]] = make_uchar4((unsigned char)ch[0], (unsigned char)ch[1], (unsigned char)ch[2], 0);
     }
+  }
   }
   // per-workgroup update counts (band / free) for the roofline accounting:
   // each workgroup writes its own slot (one atomic per workgroup on a shared
