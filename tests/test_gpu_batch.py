@@ -30,8 +30,8 @@ def serving_sequences():
             synth.dynamic_room(n_frames=4, width=77, height=53, n_clusters=1, seed=7, movers="in_view")]
 
 
-def run(rf, seqs, batched, start_offsets=(0, 0, 0, 0)):
-    tp, mp = rf.TrackParams(2, 6), rf.MaskParams()
+def run(rf, seqs, batched, start_offsets=(0, 0, 0, 0), tp=None):
+    tp, mp = tp or rf.TrackParams(2, 6), rf.MaskParams()
     sessions = [rf.Session(map_params(rf, s, max_blocks=1 << 16), s.poses[0]) for s in seqs]
     offs = list(start_offsets[:len(seqs)])
     steps = max(s.n + o for s, o in zip(seqs, offs))
@@ -75,6 +75,22 @@ def test_serving_resolutions_batched_equal_alone(rf):
             assert np.array_equal(x, y) and np.array_equal(x, z)
     assert all(a[6][0] == 0 for a in alone)
     assert all(a[1].any() for a in alone[:3])  # the movers are masked in every size
+
+
+def test_separate_solves_equal_fused_levenberg_marquardt(rf):
+    """The serving mix under Levenberg-Marquardt: batched, level 0 has more
+    than 3072 workgroups and solves in a launch of its own per iteration, while
+    most sessions alone solve at the start of every workgroup; poses, masks
+    and maps are bit-identical either way (the accept / reject state passes
+    between the two schedules' launches alike)."""
+    seqs = serving_sequences()
+    tp = rf.TrackParams(2, 6, lm_lambda=1e-3, adaptive=True)
+    alone = run(rf, seqs, batched=False, tp=tp)
+    mixed = run(rf, seqs, batched=True, tp=tp)
+    for a, b in zip(alone, mixed):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    assert all(a[6][0] == 0 for a in alone)
 
 
 def test_serve_loop_results_equal_alone(rf):
