@@ -257,8 +257,24 @@ __device__ __forceinline__ int find_or_claim_from(const MapDev& m, int x, int y,
   const unsigned long long key = pack_key(x, y, z);
   *claimed = false;
   uint32_t h = (home + i0) & m.bucket_mask;
+  // the keys past the known one are read two at a time (one round trip per
+  // pair); a key read early may be one that another thread has since put
+  // into an empty bucket, which the CAS below resolves as for any race
+  unsigned long long kn = kEmptyKey;
+  bool have_next = false;
   for (uint32_t i = i0; i < m.max_probe; ++i) {
-    if (i > i0) k = m.buckets[h].key;
+    if (i > i0) {
+      if (have_next) {
+        k = kn;
+        have_next = false;
+      } else {
+        k = m.buckets[h].key;
+        if (i + 1 < m.max_probe) {
+          kn = m.buckets[(h + 1) & m.bucket_mask].key;
+          have_next = true;
+        }
+      }
+    }
     if (k == key) return (int)h;
     if (k == kEmptyKey) {
       const unsigned long long old = atomicCAS(&m.buckets[h].key, kEmptyKey, key);
