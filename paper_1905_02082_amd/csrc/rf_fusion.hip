@@ -545,212 +545,213 @@ __global__ __launch_bounds__(256) void integrate_kernel(Batch b) {
       s_tent[q] = e;
     }
     __syncthreads();
-  for (uint32_t k = 0; k < nk; k += kIntegBlocks) {
-    Bucket bu[kIntegBlocks];
-    uint32_t st[kIntegBlocks];  // uniform: the whole-block test's outcome
-    uint32_t eb[kIntegBlocks];  // uniform: bucket index
-    bool live[kIntegBlocks], whole[kIntegBlocks], pend[kIntegBlocks];
-#pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) {
-      const bool in = k + i < nk;
-      const uint32_t ki = in ? k + i : k;
-      const uint32_t e = s_tent[ki];
-      bu[i].key = s_tkey[ki];
-      bu[i].slot = s_tslot[ki];
-      st[i] = COMPACT ? (e & ~bucket_bits) : 0u;
-      eb[i] = e & bucket_bits;
-      whole[i] = (st[i] & kEntryWhole) != 0u;
-      // a free block: evaluated voxel by voxel from its free value, it takes
-      // a pool slot below if a voxel gets a band update
-      pend[i] = (st[i] & (kEntryWhole | kEntryFresh)) == kEntryFresh;
-      live[i] = in && (bu[i].slot < m.max_blocks || pend[i]);
-    }
-    int pix[NV];
-    uint32_t vidx[NV];
-    float X2[NV];
-    bool vis[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int i = v >> 1;
-      const int l = threadIdx.x + 256 * (v & 1);
-      const bool ok = live[i];
-      vidx[v] = (ok && !pend[i]) ? bu[i].slot * 512u + (uint32_t)l : 0u;
-      if (whole[i]) {  // a block of voxels carved whole: no projection, no pixel
-        pix[v] = 0;
-        X2[v] = 0.0f;
-        vis[v] = ok;
-        continue;
-      }
-      int bx, by, bz;
-      unpack_key(bu[i].key, bx, by, bz);
-      // X = R^T (v s - t), summed as (R0j d0 + R1j d1) + R2j d2
-      const float d0 = (float)(8 * bx + (l & 7)) * m.s - t[0];
-      const float d1 = (float)(8 * by + ((l >> 3) & 7)) * m.s - t[1];
-      const float d2 = (float)(8 * bz + (l >> 6)) * m.s - t[2];
-      const float x0 = (R[0] * d0 + R[3] * d1) + R[6] * d2;
-      const float x1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
-      const float x2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
-      bool in = ok && x2 > 0.0f;
-      // x0 / x2 and x1 / x2 from one correctly rounded reciprocal (exact
-      // quotients; x2 > 0 and the pixel test reject the rest)
-      const float iz = 1.0f / x2;
-      const float uf = f.fx * quotient_rn(x0, x2, iz) + f.cx;
-      const float vf = f.fy * quotient_rn(x1, x2, iz) + f.cy;
-      const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
-      in = in && ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H;
-      pix[v] = in ? (int)vr * f.W + (int)ur : 0;
-      X2[v] = x2;
-      vis[v] = in;
-    }
-    float D[NV], sdf[NV], W[NV];
-    uint32_t mk[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      D[v] = 0.0f;
-      mk[v] = 0u;
-      if (!whole[v >> 1]) {
-        D[v] = load_depth<DF>(f, pix[v]);
-        mk[v] = mask_src[pix[v]];
-      }
-      if (!pend[v >> 1]) VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(D[v]), "+v"(mk[v]), "+v"(sdf[v]), "+v"(W[v]));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if (!pend[v >> 1]) continue;
-      // a pending free block: every voxel starts from the free value (tau
-      // and its count; unobserved while 0)
-      const float c = (float)((st[v >> 1] >> kEntryCountShift) & 0xFFu);
-      sdf[v] = c > 0.0f ? m.tau : 0.0f;
-      W[v] = c;
-    }
-    // RN(1 / (W + 1)) of every voxel: from the table for the integral
-    // weights the integration writes (0 .. 255), by division otherwise
-    float rw[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int wi = (int)W[v];
-      const bool tab = wi >= 0 && wi < 256 && (float)wi == W[v];
-      rw[v] = s_rw[tab ? wi : 0];
-      if (!tab) rw[v] = 1.0f / (W[v] + 1.0f);
-    }
-    // the per-voxel rule's decision and the new sdf of every voxel
-    bool band[NV], upd[NV];
-    float nsdf[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      band[v] = false;
-      upd[v] = false;
-      float dval = m.tau;
-      if (whole[v >> 1]) {
-        upd[v] = vis[v];  // carved whole: the free-space update
-      } else if (vis[v] && D[v] > 0.0f && !(mask && mk[v])) {
-        const float eta = D[v] - X2[v];
-        if (eta >= -m.tau) {
-          const bool bnd = eta <= m.tau;
-          // the band of a measurement beyond depth_max is not integrated; the
-          // free space in front of it is carved like any other (Sec. III-D)
-          if (bnd ? (D[v] <= m.dmax) : (X2[v] <= m.dmax)) {
-            upd[v] = true;
-            band[v] = bnd;
-            dval = bnd ? eta : m.tau;
-          }
-        }
-      }
-      nsdf[v] = quotient_rn(W[v] * sdf[v] + dval, W[v] + 1.0f, rw[v]);
-    }
-    // pending free blocks: a band update anywhere in the block gives it a pool
-    // slot (all its voxels are then written); otherwise the frame counts for
-    // the block if it carves every voxel of it, and leaves it as it is if not
-    // (its value stands for space observed free in all of its voxels)
-    bool fresh[kIntegBlocks];
-#pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) fresh[i] = false;
-    bool any_pend = false;
-#pragma unroll
-    for (int i = 0; i < kIntegBlocks; ++i) any_pend = any_pend || pend[i];
-    if (COMPACT && any_pend) {  // uniform
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-        if (pend[v >> 1] && live[v >> 1] && (band[v] || !upd[v])) atomicOr(&s_pf[v >> 1], band[v] ? 1u : 2u);
-      __syncthreads();
-      if (threadIdx.x < kIntegBlocks) {
-        const int i = threadIdx.x;
-        uint32_t slot = kInvalidSlot;
-        if (pend[i] && live[i]) {
-          const uint32_t fl = s_pf[i];
-          const uint32_t c = (st[i] >> kEntryCountShift) & 0xFFu;
-          if (fl & 1u) {
-            slot = atomicAdd(&m.st->n_blocks, 1u);
-            if (slot < m.max_blocks) {
-              m.block_keys[slot] = bu[i].key;
-            } else {
-              slot = kInvalidSlot;
-              atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
-            }
-            m.buckets[eb[i]].slot = slot;
-          } else if (!(fl & 2u)) {
-            m.buckets[eb[i]].slot = kFreeSlot | min(c + 1u, (uint32_t)m.max_weight);
-          }
-        }
-        s_pslot[i] = slot;
-        s_pf[i] = 0u;
-      }
-      __syncthreads();
+    for (uint32_t k = 0; k < nk; k += kIntegBlocks) {
+      Bucket bu[kIntegBlocks];
+      uint32_t st[kIntegBlocks];  // uniform: the whole-block test's outcome
+      uint32_t eb[kIntegBlocks];  // uniform: bucket index
+      bool live[kIntegBlocks], whole[kIntegBlocks], pend[kIntegBlocks];
 #pragma unroll
       for (int i = 0; i < kIntegBlocks; ++i) {
-        if (!pend[i]) continue;
-        const uint32_t slot = s_pslot[i];
-        fresh[i] = slot < m.max_blocks;
-        if (fresh[i]) bu[i].slot = slot;
+        const bool in = k + i < nk;
+        const uint32_t ki = in ? k + i : k;
+        const uint32_t e = s_tent[ki];
+        bu[i].key = s_tkey[ki];
+        bu[i].slot = s_tslot[ki];
+        st[i] = COMPACT ? (e & ~bucket_bits) : 0u;
+        eb[i] = e & bucket_bits;
+        whole[i] = (st[i] & kEntryWhole) != 0u;
+        // a free block: evaluated voxel by voxel from its free value, it takes
+        // a pool slot below if a voxel gets a band update
+        pend[i] = (st[i] & (kEntryWhole | kEntryFresh)) == kEntryFresh;
+        live[i] = in && (bu[i].slot < m.max_blocks || pend[i]);
+      }
+      int pix[NV];
+      uint32_t vidx[NV];
+      float X2[NV];
+      bool vis[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int i = v >> 1;
+        const int l = threadIdx.x + 256 * (v & 1);
+        const bool ok = live[i];
+        vidx[v] = (ok && !pend[i]) ? bu[i].slot * 512u + (uint32_t)l : 0u;
+        if (whole[i]) {  // a block of voxels carved whole: no projection, no pixel
+          pix[v] = 0;
+          X2[v] = 0.0f;
+          vis[v] = ok;
+          continue;
+        }
+        int bx, by, bz;
+        unpack_key(bu[i].key, bx, by, bz);
+        // X = R^T (v s - t), summed as (R0j d0 + R1j d1) + R2j d2
+        const float d0 = (float)(8 * bx + (l & 7)) * m.s - t[0];
+        const float d1 = (float)(8 * by + ((l >> 3) & 7)) * m.s - t[1];
+        const float d2 = (float)(8 * bz + (l >> 6)) * m.s - t[2];
+        const float x0 = (R[0] * d0 + R[3] * d1) + R[6] * d2;
+        const float x1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
+        const float x2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
+        bool in = ok && x2 > 0.0f;
+        // x0 / x2 and x1 / x2 from one correctly rounded reciprocal (exact
+        // quotients; x2 > 0 and the pixel test reject the rest)
+        const float iz = 1.0f / x2;
+        const float uf = f.fx * quotient_rn(x0, x2, iz) + f.cx;
+        const float vf = f.fy * quotient_rn(x1, x2, iz) + f.cy;
+        const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
+        in = in && ur >= 0.0f && ur < (float)f.W && vr >= 0.0f && vr < (float)f.H;
+        pix[v] = in ? (int)vr * f.W + (int)ur : 0;
+        X2[v] = x2;
+        vis[v] = in;
+      }
+      float D[NV], sdf[NV], W[NV];
+      uint32_t mk[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        D[v] = 0.0f;
+        mk[v] = 0u;
+        if (!whole[v >> 1]) {
+          D[v] = load_depth<DF>(f, pix[v]);
+          mk[v] = mask_src[pix[v]];
+        }
+        if (!pend[v >> 1]) VoxelStore<STORAGE>::load(m, vidx[v], sdf[v], W[v]);
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        if (fresh[v >> 1]) vidx[v] = bu[v >> 1].slot * 512u + (uint32_t)(threadIdx.x + 256 * (v & 1));
-    }
-    // stores: updated voxels; every voxel of a block that takes its pool slot now
+      for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(D[v]), "+v"(mk[v]), "+v"(sdf[v]), "+v"(W[v]));
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int i = v >> 1;
-      if (pend[i] && !fresh[i]) {
-        band[v] = false;  // stays a free block: nothing stored
-        continue;
+      for (int v = 0; v < NV; ++v) {
+        if (!pend[v >> 1]) continue;
+        // a pending free block: every voxel starts from the free value (tau
+        // and its count; unobserved while 0)
+        const float c = (float)((st[v >> 1] >> kEntryCountShift) & 0xFFu);
+        sdf[v] = c > 0.0f ? m.tau : 0.0f;
+        W[v] = c;
       }
-      if (upd[v]) {
-        VoxelStore<STORAGE>::store(m, vidx[v], nsdf[v], fminf(W[v] + 1.0f, m.max_weight));
-        nb += band[v];
-        nf += !band[v];
-      } else if (fresh[i]) {
-        VoxelStore<STORAGE>::store(m, vidx[v], sdf[v], W[v]);
+      // RN(1 / (W + 1)) of every voxel: from the table for the integral
+      // weights the integration writes (0 .. 255), by division otherwise
+      float rw[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int wi = (int)W[v];
+        const bool tab = wi >= 0 && wi < 256 && (float)wi == W[v];
+        rw[v] = s_rw[tab ? wi : 0];
+        if (!tab) rw[v] = 1.0f / (W[v] + 1.0f);
+      }
+      // the per-voxel rule's decision and the new sdf of every voxel
+      bool band[NV], upd[NV];
+      float nsdf[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        band[v] = false;
+        upd[v] = false;
+        float dval = m.tau;
+        if (whole[v >> 1]) {
+          upd[v] = vis[v];  // carved whole: the free-space update
+        } else if (vis[v] && D[v] > 0.0f && !(mask && mk[v])) {
+          const float eta = D[v] - X2[v];
+          if (eta >= -m.tau) {
+            const bool bnd = eta <= m.tau;
+            // the band of a measurement beyond depth_max is not integrated; the
+            // free space in front of it is carved like any other (Sec. III-D)
+            if (bnd ? (D[v] <= m.dmax) : (X2[v] <= m.dmax)) {
+              upd[v] = true;
+              band[v] = bnd;
+              dval = bnd ? eta : m.tau;
+            }
+          }
+        }
+        nsdf[v] = quotient_rn(W[v] * sdf[v] + dval, W[v] + 1.0f, rw[v]);
+      }
+      // pending free blocks: a band update anywhere in the block gives it a pool
+      // slot (all its voxels are then written); otherwise the frame counts for
+      // the block if it carves every voxel of it, and leaves it as it is if not
+      // (its value stands for space observed free in all of its voxels)
+      bool fresh[kIntegBlocks];
+#pragma unroll
+      for (int i = 0; i < kIntegBlocks; ++i) fresh[i] = false;
+      bool any_pend = false;
+#pragma unroll
+      for (int i = 0; i < kIntegBlocks; ++i) any_pend = any_pend || pend[i];
+      if (COMPACT && any_pend) {  // uniform
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (pend[v >> 1] && live[v >> 1] && (band[v] || !upd[v])) atomicOr(&s_pf[v >> 1], band[v] ? 1u : 2u);
+        __syncthreads();
+        if (threadIdx.x < kIntegBlocks) {
+          const int i = threadIdx.x;
+          uint32_t slot = kInvalidSlot;
+          if (pend[i] && live[i]) {
+            const uint32_t fl = s_pf[i];
+            const uint32_t c = (st[i] >> kEntryCountShift) & 0xFFu;
+            if (fl & 1u) {
+              slot = atomicAdd(&m.st->n_blocks, 1u);
+              if (slot < m.max_blocks) {
+                m.block_keys[slot] = bu[i].key;
+              } else {
+                slot = kInvalidSlot;
+                atomicOr(&m.st->flags, (uint32_t)RF_FLAG_POOL_FULL);
+              }
+              m.buckets[eb[i]].slot = slot;
+            } else if (!(fl & 2u)) {
+              m.buckets[eb[i]].slot = kFreeSlot | min(c + 1u, (uint32_t)m.max_weight);
+            }
+          }
+          s_pslot[i] = slot;
+          s_pf[i] = 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kIntegBlocks; ++i) {
+          if (!pend[i]) continue;
+          const uint32_t slot = s_pslot[i];
+          fresh[i] = slot < m.max_blocks;
+          if (fresh[i]) bu[i].slot = slot;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (fresh[v >> 1]) vidx[v] = bu[v >> 1].slot * 512u + (uint32_t)(threadIdx.x + 256 * (v & 1));
+      }
+      // stores: updated voxels; every voxel of a block that takes its pool slot now
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int i = v >> 1;
+        if (pend[i] && !fresh[i]) {
+          band[v] = false;  // stays a free block: nothing stored
+          continue;
+        }
+        if (upd[v]) {
+          VoxelStore<STORAGE>::store(m, vidx[v], nsdf[v], fminf(W[v] + 1.0f, m.max_weight));
+          nb += band[v];
+          nf += !band[v];
+        } else if (fresh[i]) {
+          VoxelStore<STORAGE>::store(m, vidx[v], sdf[v], W[v]);
+        }
+      }
+      uint32_t cold[NV], cpx[NV][3];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        cold[v] = 0u;
+        cpx[v][0] = cpx[v][1] = cpx[v][2] = 0u;
+        if (!band[v]) continue;
+        if (!fresh[v >> 1]) cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
+        const uint8_t* px = f.rgb + 3 * pix[v];
+        cpx[v][0] = px[0];
+        cpx[v][1] = px[1];
+        cpx[v][2] = px[2];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]), "+v"(cpx[v][2]));
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (!band[v]) continue;
+        const float Wv = W[v], Wn = W[v] + 1.0f;
+        float ch[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          ch[q] = fminf(255.0f, fmaxf(0.0f, rintf(quotient_rn(
+                                                Wv * (float)((cold[v] >> (8 * q)) & 0xFFu) + (float)cpx[v][q], Wn,
+                                                rw[v]))));
+        m.rgb[vidx[v]] = make_uchar4((unsigned char)ch[0], (unsigned char)ch[1], (unsigned char)ch[2], 0);
       }
     }
-    uint32_t cold[NV], cpx[NV][3];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      cold[v] = 0u;
-      cpx[v][0] = cpx[v][1] = cpx[v][2] = 0u;
-      if (!band[v]) continue;
-      if (!fresh[v >> 1]) cold[v] = reinterpret_cast<const uint32_t*>(m.rgb)[vidx[v]];
-      const uint8_t* px = f.rgb + 3 * pix[v];
-      cpx[v][0] = px[0];
-      cpx[v][1] = px[1];
-      cpx[v][2] = px[2];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(cold[v]), "+v"(cpx[v][0]), "+v"(cpx[v][1]), "+v"(cpx[v][2]));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if (!band[v]) continue;
-      const float Wv = W[v], Wn = W[v] + 1.0f;
-      float ch[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-        ch[q] = fminf(255.0f, fmaxf(0.0f, rintf(quotient_rn(Wv * (float)((cold[v] >> (8 * q)) & 0xFFu) + (float)cpx[v][q],
-                                                            Wn, rw[v]))));
-      m.rgb[vidx[v]] = make_uchar4((unsigned char)ch[0], (unsigned char)ch[1], (unsigned char)ch[2], 0);
-    }
-  }
   }
   // per-workgroup update counts (band / free) for the roofline accounting:
   // each workgroup writes its own slot (one atomic per workgroup on a shared
