@@ -541,7 +541,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (sessions would shard "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (sessions would shard "
               "across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -51,7 +51,7 @@ typedef int32_t rf_status;
 #define RF_EINVAL (-1)       /* bad argument or shape */
 #define RF_ENOMEM (-2)       /* arena or caller buffer too small */
 #define RF_EDEVICE (-3)      /* a HIP runtime call failed */
-#define RF_EUNSUPPORTED (-4) /* valid request this build does not support */
+#define RF_EUNSUPPORTED (-4) /* valid request the library does not support */
 
 /* sticky device-side condition bits (map_status, rf_track_stats.flags) */
 #define RF_FLAG_POOL_FULL 0x1u        /* a block could not get a pool slot; its voxels are skipped */
