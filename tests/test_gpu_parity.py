@@ -574,6 +574,42 @@ def test_frame_list_beyond_a_listing_run(rf):
         assert flags == 0 and nb == len(F_orc)
 
 
+def test_batched_integration_beyond_a_workgroup_table(rf):
+    """Eight maps allocated and integrated in one batch on a frame facing a
+    wall at 2.0 m with 0.5 cm voxels (~53 k listed blocks per map): each map
+    gets 192 integration workgroups, so a workgroup's share of the list
+    (~275 blocks) exceeds the 256 entries it holds in LDS at a time and its
+    second chunk runs too.  Two of the maps are compared with the FP32
+    mirror: blocks, sdf, weight and colour bit-exact."""
+    from paper_1905_02082_amd import _native as N
+    W, H = 640, 480
+    intr = (525.0, 525.0, 319.5, 239.5)
+    depth = np.full((H, W), 2000, np.uint16)
+    rgb = np.random.default_rng(12).integers(0, 256, (H, W, 3), dtype=np.uint8)
+    T = np.eye(4)
+    T[:3, 3] = [0.013, -0.021, 0.007]
+    o32 = O.OracleMap(0.005, 0.03, 3.5, 255, 2, real_bits=32)
+    fr = O.Frame(depth, rgb, *intr, depth_scale=0.001)
+    F_orc = o32.allocate(fr, T)
+    o32.integrate(fr, T)
+    assert len(F_orc) > 256 * 192
+    params = rf.MapParams(0.005, 0.03, 3.5, 1 << 18, 1 << 16, 255, 2, "fp32", W * H)
+    sessions = [rf.Session(params, T) for _ in range(8)]
+    frames = [rf.Frame.from_numpy(depth, rgb, *intr, depth_scale=0.001)] * 8
+    L = N.load()
+    assert L.hashmap_allocate_batch(rf._jobs(sessions, frames), 8, None) == 0
+    assert L.integrate_frame_batch(rf._jobs(sessions, frames), 8, None) == 0
+    torch.cuda.synchronize()
+    km, sm, wm, cm = o32.export()
+    for s in (sessions[0], sessions[7]):
+        assert s.map.status() == (0, len(F_orc))
+        gk, gs, gw, gc = gpu_export_sorted(s.map)
+        assert np.array_equal(gk, km)
+        np.testing.assert_array_equal(gs, sm.astype(np.float32))
+        np.testing.assert_array_equal(gw, wm.astype(np.float32))
+        np.testing.assert_array_equal(gc, cm)
+
+
 def test_track_is_deterministic(rf, room):
     """Order-independent fixed-point reduction: repeated runs are bit-identical."""
     m, _, _ = integrate_teacher_forced(rf, room, range(2))
